@@ -1,0 +1,207 @@
+"""Pins for the oracle's whole construction, encoding and query.
+
+P1 bijection by brute force on small inputs, P2 minimality (naive search
+equals the bitmask/rotation search), order independence, duplicate
+rejection, the Golomb-Rice parameter against a brute-force minimisation of
+the expected code length, the Elias-Fano size bound, a hand-checked layout,
+and bits per key against the paper's tables and the log2(e) lower bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from closed_forms import rice_length
+from conftest import golden
+from paper_2212_09562_amd import keygen
+
+
+def _is_perm(r, n):
+    return np.array_equal(np.sort(np.asarray(r, dtype=np.uint64)), np.arange(n, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("rotation", [False, True])
+@pytest.mark.parametrize("l,b", [(2, 1), (3, 2), (4, 7), (5, 100), (8, 7), (8, 100), (12, 30)])
+def test_bijection_small(l, b, rotation):
+    for n in (0, 1, 2, 3, 5, 17, 100, 1000):
+        k = keygen.fingerprints(n, 1000 + n + l)
+        data, _ = oracle.build(k, l, b, rotation)
+        assert _is_perm(oracle.query(data, k), n)
+
+
+@pytest.mark.parametrize("rotation", [False, True])
+@pytest.mark.parametrize("l,b", [(4, 7), (8, 100), (6, 50)])
+def test_naive_search_equals_fast(l, b, rotation):
+    k = keygen.fingerprints(3000, 77)
+    fast, st1 = oracle.build(k, l, b, rotation)
+    naive, st2 = oracle.build(k, l, b, rotation, naive=True)
+    assert fast == naive
+    assert st1["evals_split"] == st2["evals_split"] and st1["evals_leaf"] == st2["evals_leaf"]
+
+
+def test_order_independence():
+    k = keygen.fingerprints(20000, 5)
+    perm = np.random.default_rng(0).permutation(len(k))
+    for rot in (False, True):
+        a, _ = oracle.build(k, 8, 100, rot)
+        b, _ = oracle.build(k[perm], 8, 100, rot)
+        assert a == b
+
+
+def test_duplicates_rejected():
+    k = keygen.fingerprints(1000, 6)
+    dup = k.copy()
+    # same w1 and a w0 that lands in the same bucket (differs only in bit 0)
+    dup[10, 1] = dup[11, 1]
+    dup[10, 0] = dup[11, 0] ^ np.uint64(1)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build(dup, 8, 100, True)
+    assert e.value.code == -2
+    # the same w1 in different buckets is fine
+    ok = k.copy()
+    ok[10, 1] = ok[11, 1]
+    ok[10, 0] = ok[11, 0] ^ np.uint64(1 << 63)
+    data, _ = oracle.build(ok, 8, 100, True)
+    assert _is_perm(oracle.query(data, ok), len(ok))
+
+
+def test_invalid_arguments():
+    k = keygen.fingerprints(10, 1)
+    for l, b in ((1, 100), (25, 100), (8, 0), (8, 4097)):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.build(k, l, b, True)
+        assert e.value.code == -1
+
+
+def test_tau_is_optimal_rice_parameter():
+    """tau (reading R17) minimises the expected Rice code length of a
+    geometric value with the node's success probability."""
+    for l in (2, 3, 5, 8, 12, 16, 24):
+        for m in list(range(2, 200)) + list(range(200, 4200, 97)):
+            x = oracle.tau_log2arg(m, l)
+            lq = math.log((math.sqrt(5) - 1) / 2) / 2 ** x  # ln(1 - p)
+            p = -math.expm1(lq)
+            best = min(range(64), key=lambda t: rice_length(p, t))
+            assert oracle.tau(m, l) == best, (l, m)
+
+
+def test_tau_never_near_a_rounding_boundary():
+    worst = 1.0
+    for l in range(2, 25):
+        for m in range(2, 4700):
+            x = oracle.tau_log2arg(m, l)
+            worst = min(worst, abs(x - round(x)))
+    assert worst > 1e-9
+
+
+def _parse(data):
+    w = np.frombuffer(data, dtype=np.uint64)
+    hdr = {"magic": int(w[0]), "version": int(w[1]) & 0xFFFFFFFF, "flags": int(w[1]) >> 32,
+           "n": int(w[2]), "l": int(w[3]) & 0xFFFFFFFF, "b": int(w[3]) >> 32, "nb": int(w[4])}
+    at = 5
+    efs = []
+    for _ in range(2):
+        N, U, L, lw, ub, uw = (int(x) for x in w[at:at + 6])
+        efs.append({"N": N, "U": U, "L": L, "lower": w[at + 6:at + 6 + lw], "upper_bits": ub,
+                    "upper": w[at + 6 + lw:at + 6 + lw + uw]})
+        at += 6 + lw + uw
+    gr_bits, gr_words = int(w[at]), int(w[at + 1])
+    gr = w[at + 2:at + 2 + gr_words]
+    assert at + 2 + gr_words == len(w)
+    return hdr, efs, gr_bits, gr
+
+
+def _bits(words, start, count):
+    return [int(words[(start + i) // 64]) >> ((start + i) % 64) & 1 for i in range(count)]
+
+
+def test_worked_example_single_leaf():
+    """Two keys, b = 2: one bucket holding one leaf of size 2 with tau = 0, so
+    the record is v zero bits and a one; the Elias-Fano sequences are laid out
+    by hand from Sec. 2.1."""
+    k = keygen.fingerprints(2, 3)
+    for rot in (False, True):
+        data, _ = oracle.build(k, 8, 2, rot)
+        hdr, (efc, efp), gr_bits, gr = _parse(data)
+        assert hdr["n"] == 2 and hdr["nb"] == 1 and hdr["flags"] == int(rot)
+        v, _ = oracle.leaf_search(k[:, 1], (k[:, 0] & np.uint64(1)).astype(np.uint8), 0,
+                                  oracle.LEAF_ROT if rot else oracle.LEAF_BRUTE)
+        assert oracle.tau(2, 8) == 0
+        assert gr_bits == v + 1
+        assert _bits(gr, 0, v + 1) == [0] * v + [1]
+        # C = (0, 2): N = 2, U = 2, L = 0, upper bits at 0 + 0 and 2 + 1
+        assert (efc["N"], efc["U"], efc["L"], efc["upper_bits"]) == (2, 2, 0, 4)
+        assert int(efc["upper"][0]) == 0b1001
+        # P = (0, v + 1)
+        U = v + 1
+        L = 0
+        while (U >> (L + 1)) >= 2:
+            L += 1
+        assert (efp["N"], efp["U"], efp["L"]) == (2, U, L)
+        assert _bits(efp["lower"], 0, 2 * L) == _bits(np.array([U << L], dtype=np.uint64), 0, 2 * L)
+        assert efp["upper_bits"] == (U >> L) + 2
+        assert _bits(efp["upper"], 0, efp["upper_bits"]) == [1] + [0] * (U >> L) + [1]
+
+
+def test_worked_example_split_with_singleton():
+    """m = 9 at l = 8: a lower node with parts (8, 1); the singleton child
+    stores nothing (reading R10), so the bucket holds two values: the split
+    seed, then the leaf."""
+    k = keygen.fingerprints(9, 4)
+    data, st = oracle.build(k, 8, 9, True)
+    vals = oracle.bucket_values(data, 0)
+    assert len(vals) == 2 and st["nodes_split"] == 1 and st["nodes_leaf"] == 1
+    assert oracle.children(9, 8) == [8, 1]
+    assert oracle.preorder_sizes(9, 8) == [9, 8]
+    s = oracle.split_search(k[:, 1], 8, 0)
+    assert vals[0] == s
+    assert _is_perm(oracle.query(data, k), 9)
+
+
+def test_record_roundtrip_and_layout():
+    """Values decoded from the bytes equal the values the build chose, and the
+    Golomb-Rice vector is the concatenation of the per-bucket records."""
+    k = keygen.fingerprints(5000, 8)
+    data, _ = oracle.build(k, 8, 100, True)
+    hdr, (efc, efp), gr_bits, gr = _parse(data)
+    sel = [0, 1, 7, hdr["nb"] - 1]
+    recs, _ = oracle.build_buckets(k, 8, 100, True, sel)
+    # decode P_j by walking the upper bits of EF(P)
+    ub = _bits(efp["upper"], 0, efp["upper_bits"])
+    ones = [i for i, x in enumerate(ub) if x]
+    lows = _bits(efp["lower"], 0, efp["N"] * efp["L"])
+    Pj = [((ones[i] - i) << efp["L"]) | sum(lows[i * efp["L"] + t] << t for t in range(efp["L"]))
+          for i in range(efp["N"])]
+    assert Pj[-1] == gr_bits
+    for (j, size, vals, words, nbits) in recs:
+        assert np.array_equal(oracle.bucket_values(data, j), vals)
+        assert Pj[j + 1] - Pj[j] == nbits
+        assert _bits(gr, Pj[j], nbits) == _bits(words, 0, nbits)
+
+
+def test_elias_fano_size_bound():
+    for n, b in ((100000, 100), (50000, 7), (3000, 1000)):
+        k = keygen.fingerprints(n, 9)
+        data, _ = oracle.build(k, 5, b, True)
+        _, efs, _, _ = _parse(data)
+        for ef in efs:
+            N, U = ef["N"], ef["U"]
+            bits = N * ef["L"] + ef["upper_bits"]
+            assert bits <= N * (2 + max(0, math.ceil(math.log2(max(U, 1) / N)))) + 1
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("rotation", [False, True])
+def test_bits_per_key(rotation):
+    """Space at l = 8, b = 100 is above log2(e) (Sec. 1) and within 0.06 bits
+    of the paper's table (tab:queries; the paper's combined Elias-Fano and
+    string keys account for the gap)."""
+    n = 100000
+    k = keygen.fingerprints(n, 1)
+    data, _ = oracle.build(k, 8, 100, rotation)
+    bits = len(data) * 8 / n
+    assert bits >= math.log2(math.e)
+    paper = {(r[2]): float(r[3]) for r in golden("bits_per_object.txt") if r[0] == "8"}
+    assert abs(bits - paper["rotation" if rotation else "brute"]) < 0.06
+    assert _is_perm(oracle.query(data, k), n)
