@@ -1,0 +1,145 @@
+#!/usr/bin/env python3
+"""Benchmark: RecSplit construction of 10^7 keys at l = 16, b = 2000 on one MI355X.
+
+One step = one whole construction (bucket sort, duplicate check, split and
+leaf seed searches with rotation fitting, Golomb-Rice / Elias-Fano encoding,
+copy of the encoded bytes to the host) over 10^7 uniform random 128-bit
+fingerprints that are resident in HBM before the timed region starts.
+
+Prints one JSON line.  `roofline` prices the seed-search kernel (the
+dominant one) on the integer-VALU roofline: achieved = useful hash
+evaluations x full-rate issue slots per evaluation / search-kernel time,
+with the slot cost of each instruction class measured live by the library's
+calibration kernels; peak = 256 CU x 64 lanes x 2.4 GHz.  `cpu_baseline` is
+the CPU oracle timed on a bounded sample of the same key set.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MPHF construction keys/sec at ℓ=16,b=2000 (bit-exact) + % int-ALU roofline"
+PEAK_LANE_OPS = 256 * 64 * 2.4e9  # full-rate 32-bit VALU lane operations per second
+
+# One hash evaluation plus its position/count update, as issued by the
+# search kernel's inner loop (per key, per lane).
+INSTRUCTION_MIX = {
+    "lshl_add_u64": 1,  # w1 + seed identifier (64-bit)
+    "lshrrev_b64": 2,   # z >> 30, z >> 27
+    "xor_b32": 5,       # the two 64-bit xorshifts, final xorshift of the top word
+    "mad_u64_u32": 1,   # first multiply: low x low (64-bit result)
+    "mul_lo_u32": 4,    # cross terms of both multiplies
+    "mul_hi_u32": 2,    # top word of the second multiply; reduction to a position
+    "add3_u32": 2,      # high-word sums of both multiplies
+    "add_u32": 2,       # shift of the top word; bit / counter update
+}
+
+WORKLOAD = {"n": 10_000_000, "leaf_size": 16, "bucket_size": 2000, "rotation": True, "seed": 3}
+
+
+def slots_per_eval(rates: dict) -> float:
+    ref = rates["add_u32"]
+    return sum(n * ref / rates[k] for k, n in INSTRUCTION_MIX.items())
+
+
+def cpu_baseline(keys, l, b, buckets):
+    import oracle
+
+    t0 = time.perf_counter()
+    recs, st = oracle.build_buckets(keys, l, b, True, buckets)
+    dt = time.perf_counter() - t0
+    nkeys = sum(r[1] for r in recs)
+    return {"value": nkeys / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"buckets {buckets[0]}..{buckets[-1]} ({nkeys} keys) of the same "
+                      f"{len(keys)}-key set, whole construction of those buckets incl. bucketing "
+                      f"all keys, single thread",
+            "seconds": dt, "useful_evals_per_s": (st["evals_split"] + st["evals_leaf"]) / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=WORKLOAD["n"])
+    ap.add_argument("--cpu-buckets", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the construction is not "
+              "sharded across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2212_09562_amd import keygen, recsplit
+
+    l, b, rot = WORKLOAD["leaf_size"], WORKLOAD["bucket_size"], WORKLOAD["rotation"]
+    n = args.n
+    keys = keygen.fingerprints(n, WORKLOAD["seed"])
+    dev = torch.from_numpy(keys.view(np.int64)).cuda()
+    torch.cuda.synchronize()
+    rates = recsplit.calibrate_valu()
+    w_alg = slots_per_eval(rates)
+
+    for _ in range(args.warmup):
+        recsplit.build(dev, l, b, rot).free()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f = recsplit.build(dev, l, b, rot)
+        stats.append(f.stats())
+        f.free()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    st = stats[-1]
+    evals = st["useful_evals_split"] + st["useful_evals_leaf"]
+    ms_search = sum(s["ms_search"] for s in stats) / len(stats)
+    evals_per_s = evals / (ms_search * 1e-3)
+    achieved = evals_per_s * w_alg / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    out = {
+        "metric": METRIC,
+        "value": n * args.steps / secs,
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic: uniform random 128-bit fingerprints (SplitMix64, seed 3)",
+        "config": {"workload": f"RecSplit construction, n={n}, l={l}, b={b}, rotation fitting",
+                   "n": n, "leaf_size": l, "bucket_size": b, "rotation": rot,
+                   "global_batch": n, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "rs_search_kernel", "ms_per_launch": ms_search,
+                     "useful_hash_evals": evals, "slots_per_eval": w_alg,
+                     "hash_evals_per_s": evals_per_s,
+                     "calibrated_hash_loop_evals_per_s": rates["hash_evals"]},
+        "bits_per_key": st["bytes"] * 8 / n,
+        "stage_ms": {k: sum(s[k] for s in stats) / len(stats)
+                     for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},
+        "valu_rates": rates,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(keys, l, b, list(range(args.cpu_buckets)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,146 @@
+/*
+ * recsplit.h -- C ABI of the MI355X RecSplit construction library.
+ *
+ * RecSplit (Esposito et al., ALENEX 2020) as extended by Bez, Kurpicz,
+ * Lehmann and Sanders, "High Performance Construction of RecSplit Based
+ * Minimal Perfect Hash Functions" (arXiv 2212.09562).  A minimal perfect hash
+ * function maps a set S of n keys bijectively onto [0, n); a key outside S
+ * maps to some value in [0, n) or beyond, without error (Sec. 1).
+ *
+ * Keys are 128-bit master hash codes (Sec. 2.2: every object is first hashed
+ * to a uniform fingerprint; Sec. 6 uses random 128-bit integers directly).
+ * The first word selects the bucket and the leaf half A/B; the second word is
+ * hashed by the splitting and bijection searches.
+ *
+ * Every entry point returns RS_OK (0) or a negative RS_ERR_* code and leaves
+ * its out-parameters untouched (or NULL) on error.  The build runs entirely
+ * in HIP kernels on the current HIP device; the library owns every rs_mphf
+ * it returns and the caller owns every buffer it passes in.
+ */
+#ifndef RECSPLIT_H
+#define RECSPLIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* w0: bucket selector (top bits) and A/B class (bit 0); w1: hashed word. */
+typedef struct {
+  uint64_t w0, w1;
+} rs_key128;
+
+typedef struct rs_mphf rs_mphf;
+
+enum {
+  RS_OK = 0,
+  RS_ERR_INVALID_ARG = -1,  /* leaf size, bucket size, n or a pointer out of range */
+  RS_ERR_DUPLICATE = -2,    /* two keys of one bucket share w1: no bijection exists */
+  RS_ERR_OOM = -3,          /* device or host allocation failed */
+  RS_ERR_DEVICE = -4,       /* a HIP call failed, or the device scheduler stalled */
+  RS_ERR_CORRUPT = -5,      /* serialised bytes fail validation */
+  RS_ERR_SEARCH_LIMIT = -6, /* a seed search passed its bug-guard limit */
+  RS_ERR_UNSUPPORTED = -7   /* a bucket holds more keys than RS_MAX_BUCKET_KEYS */
+};
+
+enum {
+  RS_FLAG_ROTATION = 1u,       /* leaves use rotation fitting (Sec. 4); otherwise brute force */
+  RS_FLAG_KEYS_ON_DEVICE = 2u, /* keys (and query output) are device pointers */
+  RS_FLAG_KEEP_VALUES = 4u     /* keep a host copy of every node value (rs_debug_node_values) */
+};
+
+#define RS_MAX_LEAF_SIZE 24u
+#define RS_MAX_BUCKET_SIZE 4096u
+#define RS_MAX_BUCKET_KEYS 8192u
+
+/*
+ * Build the minimal perfect hash function of n distinct keys (Sec. 2.2:
+ * bucketing, one splitting tree per bucket whose inner nodes get the
+ * smallest seed that splits their keys into the prescribed part sizes and
+ * whose leaves get the smallest bijection value, Sec. 4 rotation fitting,
+ * Golomb-Rice and Elias-Fano encoding).
+ *
+ * keys:        n rs_key128, host memory, or device memory with
+ *              RS_FLAG_KEYS_ON_DEVICE (read on the null stream, which orders
+ *              after work on the legacy default stream).  Read only.
+ * n:           0 <= n < 2^40.
+ * leaf_size:   l, 2 <= l <= 24.
+ * bucket_size: b, the expected bucket size, 1 <= b <= 4096; nb = max(1, ceil(n/b)).
+ * flags:       RS_FLAG_*.
+ * out:         receives the new structure; release with rs_free.
+ *
+ * Errors: RS_ERR_INVALID_ARG, RS_ERR_DUPLICATE (some bucket holds two keys
+ * with the same w1), RS_ERR_UNSUPPORTED (a bucket of more than
+ * RS_MAX_BUCKET_KEYS keys), RS_ERR_OOM, RS_ERR_DEVICE, RS_ERR_SEARCH_LIMIT.
+ * The result depends only on the key set, l, b and RS_FLAG_ROTATION: it is
+ * identical for any key order and any launch configuration.
+ */
+int rs_build(const rs_key128 *keys, uint64_t n, uint32_t leaf_size, uint32_t bucket_size,
+             uint32_t flags, rs_mphf **out);
+
+/*
+ * Evaluate the function on n keys (Sec. 2.2 "Query": bucket, tree descent,
+ * leaf position; Sec. 4: keys of B add the rotation modulo the leaf size).
+ * Runs in a HIP kernel.  keys/out are host pointers, or device pointers with
+ * RS_FLAG_KEYS_ON_DEVICE.  out[i] in [0, n) for every key of the built set,
+ * and the ranks of the built set are a permutation of [0, n).  Thread safe.
+ */
+int rs_query(const rs_mphf *f, const rs_key128 *keys, uint64_t n, uint64_t *out, uint32_t flags);
+
+/*
+ * Serialised bytes (little-endian 64-bit words): header, Elias-Fano sequence
+ * of the bucket prefix sums, Elias-Fano sequence of the record bit offsets,
+ * Golomb-Rice bit vector.  *bytes stays valid until rs_free(f).
+ */
+int rs_serialize(const rs_mphf *f, const uint8_t **bytes, uint64_t *nbytes);
+
+/* Rebuild a queryable structure from serialised bytes (copied).
+ * RS_ERR_CORRUPT when the header or the section sizes do not validate. */
+int rs_deserialize(const uint8_t *bytes, uint64_t nbytes, rs_mphf **out);
+
+/* Node values of one bucket in preorder, as chosen by the build (requires
+ * RS_FLAG_KEEP_VALUES at build time).  *count receives the number of values;
+ * RS_ERR_INVALID_ARG when cap is too small or the bucket does not exist. */
+int rs_debug_node_values(const rs_mphf *f, uint64_t bucket, uint64_t *vals, uint64_t cap,
+                         uint64_t *count);
+
+/* Counters and per-stage device times (HIP events on the build's stream) of
+ * the build that produced f; zero for a deserialised structure. */
+typedef struct {
+  uint64_t n, nb, nodes, split_nodes, leaf_nodes;
+  uint64_t useful_evals_split; /* (s+1) * m per inner node */
+  uint64_t useful_evals_leaf;  /* (v+1) * m per brute leaf, (floor(v/m)+1) * m per rotation leaf */
+  uint64_t gr_bits, bytes;
+  uint32_t max_bucket, workers;
+  double ms_sort, ms_search, ms_encode, ms_total;
+} rs_stats;
+
+int rs_get_stats(const rs_mphf *f, rs_stats *st);
+
+/*
+ * Measurement helper for the integer roofline (not part of construction).
+ * Issue rates of the VALU instruction classes a hash evaluation is made of,
+ * in lane-operations per second on the current device, each measured over
+ * independent dependency chains at full occupancy; and the rate of the hash
+ * trial sequence itself (16 keys in registers, no memory), in hash
+ * evaluations per second.  Runs a few short kernels; no other side effects.
+ */
+typedef struct {
+  double add_u32, xor_b32, mul_lo_u32, mul_hi_u32, mad_u64_u32, lshrrev_b64, lshl_add_u64,
+      add3_u32;
+  double hash_evals;
+  uint32_t compute_units;
+} rs_valu_rates;
+
+int rs_calibrate_valu(rs_valu_rates *out);
+
+void rs_free(rs_mphf *f);
+
+const char *rs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RECSPLIT_H */

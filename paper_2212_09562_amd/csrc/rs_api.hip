@@ -1,0 +1,678 @@
+// C ABI of the library (include/recsplit.h): argument checks, device memory,
+// kernel orchestration, serialisation.  Every step of the construction and
+// of queries runs in the kernels of rs_prep.hip, rs_search.hip and
+// rs_encode.hip; this file only launches them and moves results.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "rs_launch.h"
+
+using namespace rs;
+
+namespace {
+
+constexpr uint64_t kMagic = 0x31564C5053434552ull;  // "RECSPLV1"
+constexpr uint64_t kVersion = 1;
+constexpr uint32_t kHeaderWords = 5;
+constexpr uint32_t kEfHeaderWords = 6;
+
+struct Buffer {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+hipError_t ensure(Buffer& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return hipSuccess;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  size_t want = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.cap = want;
+  return hipSuccess;
+}
+
+template <typename T>
+T* as(Buffer& b) {
+  return static_cast<T*>(b.p);
+}
+
+// Per-leaf-size tables, m = 0 .. kMaxBucketKeys: stored nodes of a subtree,
+// Golomb-Rice fixed bits of a subtree, and the Rice parameter of a node.
+struct Tables {
+  uint32_t* nodecnt = nullptr;
+  uint32_t* fixedbits = nullptr;
+  uint8_t* tau = nullptr;
+  std::vector<uint32_t> h_nodecnt;
+};
+
+// log of the probability that one trial succeeds at a node of size m: a leaf
+// is a bijection with probability m!/m^m; a split hits its part sizes p_j
+// with the multinomial probability m!/prod p_j! * prod (p_j/m)^p_j.
+double log_success(const Shape& s, uint32_t m) {
+  if (kind_of(s, m) == kLeaf) return lgamma((double)m + 1.0) - (double)m * log((double)m);
+  Parts p = parts_of(s, m);
+  double lp = lgamma((double)m + 1.0);
+  for (uint32_t j = 0; j < p.k; ++j) {
+    double sz = (double)part_size(p, j);
+    lp += sz * log(sz / (double)m) - lgamma(sz + 1.0);
+  }
+  return lp;
+}
+
+// Rice parameter minimising the expected code length of a geometric value
+// with success probability p (Kiely 2004): max(0, 1 + floor(log2(ln(phi-1) /
+// ln(1-p)))).  It sets the fixed width of each node's value (Sec. 2.2:
+// precomputed per layer).
+uint32_t rice_parameter(double log_p) {
+  const double p = exp(log_p);
+  const double ratio = log((sqrt(5.0) - 1.0) * 0.5) / log1p(-p);
+  const double t = 1.0 + floor(log2(ratio));
+  return t < 0.0 ? 0u : (uint32_t)t;
+}
+
+void compute_tables(uint32_t l, std::vector<uint32_t>& nodecnt, std::vector<uint32_t>& fixedbits,
+                    std::vector<uint8_t>& tau) {
+  const Shape s = make_shape(l);
+  nodecnt.assign(kTable, 0);
+  fixedbits.assign(kTable, 0);
+  tau.assign(kTable, 0);
+  for (uint32_t m = 2; m < kTable; ++m) {
+    const uint32_t t = rice_parameter(log_success(s, m));
+    tau[m] = (uint8_t)t;
+    uint32_t nc = 1, fb = t;
+    Parts p = parts_of(s, m);
+    for (uint32_t j = 0; j < p.k; ++j) {
+      const uint32_t sz = part_size(p, j);
+      nc += nodecnt[sz];
+      fb += fixedbits[sz];
+    }
+    nodecnt[m] = nc;
+    fixedbits[m] = fb;
+  }
+}
+
+uint64_t splitmix_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  return mix64(state);
+}
+
+struct Device {
+  bool ready = false;
+  int id = 0;
+  int cus = 0;
+  int wall_khz = 100000;
+  int lds_per_block = 65536;
+  uint64_t* start = nullptr;  // starting seed of depth d: SplitMix64(0) output d+1
+  Tables tables[kMaxLeaf + 1];
+  Buffer keys_in, k0, k1, cnt, fill, off, tmp, nodes, node_base, vals, msz, tasks, states, ready_f,
+      active, ctl, jobs, len, pos, qkeys, qout, sc_counts, sc_prefix;
+  hipEvent_t ev[6];
+};
+
+std::mutex g_mu;
+Device g_dev[64];
+
+int from_hip(hipError_t e) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return RS_ERR_OOM;
+  return e == hipSuccess ? RS_OK : RS_ERR_DEVICE;
+}
+
+#define HIPCHECK(expr)                     \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
+
+int device_init(Device** out) {
+  int id = 0;
+  HIPCHECK(hipGetDevice(&id));
+  if (id < 0 || id >= 64) return RS_ERR_DEVICE;
+  Device& d = g_dev[id];
+  if (!d.ready) {
+    d.id = id;
+    HIPCHECK(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, id));
+    if (hipDeviceGetAttribute(&d.lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, id) !=
+            hipSuccess ||
+        d.lds_per_block <= 0)
+      d.lds_per_block = 65536;
+    if (hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, id) != hipSuccess ||
+        d.wall_khz <= 0)
+      d.wall_khz = 100000;
+    uint64_t h[kMaxDepth], st = 0;
+    for (uint32_t i = 0; i < kMaxDepth; ++i) h[i] = splitmix_next(st);
+    HIPCHECK(hipMalloc(&d.start, sizeof h));
+    HIPCHECK(hipMemcpy(d.start, h, sizeof h, hipMemcpyHostToDevice));
+    for (int i = 0; i < 6; ++i) HIPCHECK(hipEventCreate(&d.ev[i]));
+    d.ready = true;
+  }
+  *out = &d;
+  return RS_OK;
+}
+
+int tables_for(Device& d, uint32_t l, Tables** out) {
+  Tables& t = d.tables[l];
+  if (!t.nodecnt) {
+    std::vector<uint32_t> nc, fb;
+    std::vector<uint8_t> tau;
+    compute_tables(l, nc, fb, tau);
+    HIPCHECK(hipMalloc(&t.nodecnt, kTable * sizeof(uint32_t)));
+    HIPCHECK(hipMalloc(&t.fixedbits, kTable * sizeof(uint32_t)));
+    HIPCHECK(hipMalloc(&t.tau, kTable));
+    HIPCHECK(hipMemcpy(t.nodecnt, nc.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(t.fixedbits, fb.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(t.tau, tau.data(), kTable, hipMemcpyHostToDevice));
+    t.h_nodecnt = nc;
+  }
+  *out = &t;
+  return RS_OK;
+}
+
+uint32_t ef_lowbits(uint64_t N, uint64_t U) {
+  uint32_t L = 0;
+  while (L < 63 && (U >> (L + 1)) >= N) ++L;
+  return L;
+}
+
+struct EFLayout {
+  uint64_t N, U, L, lw, ub, uw;
+  uint64_t at;  // word offset of the section header
+  uint64_t words() const { return kEfHeaderWords + lw + uw; }
+};
+
+EFLayout ef_layout(uint64_t N, uint64_t U, uint64_t at) {
+  EFLayout e;
+  e.N = N;
+  e.U = U;
+  e.L = ef_lowbits(N, U);
+  e.lw = (N * e.L + 63) / 64;
+  e.ub = (U >> e.L) + N;
+  e.uw = (e.ub + 63) / 64;
+  e.at = at;
+  return e;
+}
+
+}  // namespace
+
+struct rs_mphf {
+  std::vector<uint64_t> words;
+  uint64_t n = 0, nb = 0;
+  uint32_t l = 0, b = 0, rotation = 0;
+  EFLayout efc{}, efp{};
+  uint64_t gr_at = 0, gr_bits = 0, gr_words = 0;
+  int device = 0;
+  uint64_t* d_words = nullptr;
+  uint64_t* d_samples = nullptr;  // samples of C, then of P
+  uint64_t ns_c = 0, ns_p = 0;
+  rs_stats stats{};
+  std::vector<uint64_t> keep_vals, keep_base;
+};
+
+namespace {
+
+void release(rs_mphf* f) {
+  if (!f) return;
+  if (f->d_words) (void)hipFree(f->d_words);
+  if (f->d_samples) (void)hipFree(f->d_samples);
+  delete f;
+}
+
+// Device copy of the serialised words plus select samples of both upper
+// vectors; checks that each upper vector holds exactly N ones.
+int attach_device(Device& d, rs_mphf* f, bool words_on_device) {
+  const uint64_t nw = f->words.size();
+  if (!words_on_device) {
+    HIPCHECK(hipMalloc(&f->d_words, nw * sizeof(uint64_t)));
+    HIPCHECK(hipMemcpy(f->d_words, f->words.data(), nw * sizeof(uint64_t), hipMemcpyHostToDevice));
+  }
+  f->ns_c = (f->efc.N + 255) / 256;
+  f->ns_p = (f->efp.N + 255) / 256;
+  HIPCHECK(hipMalloc(&f->d_samples, (f->ns_c + f->ns_p + 2) * sizeof(uint64_t)));
+  const EFLayout* efs[2] = {&f->efc, &f->efp};
+  uint64_t* samp[2] = {f->d_samples, f->d_samples + f->ns_c};
+  uint64_t nsamp[2] = {f->ns_c, f->ns_p};
+  for (int i = 0; i < 2; ++i) {
+    const EFLayout& e = *efs[i];
+    const uint64_t* upper = f->d_words + e.at + kEfHeaderWords + e.lw;
+    HIPCHECK(ensure(d.sc_counts, (e.uw + 1) * sizeof(uint64_t)));
+    HIPCHECK(ensure(d.sc_prefix, (e.uw + 1) * sizeof(uint64_t)));
+    HIPCHECK(ensure(d.tmp, scan_tmp_words(e.uw + 1) * sizeof(uint64_t)));
+    HIPCHECK(select_samples(upper, e.uw, as<uint64_t>(d.sc_counts), as<uint64_t>(d.sc_prefix),
+                            as<uint64_t>(d.tmp), samp[i], nsamp[i], 0));
+    uint64_t ones = 0;
+    HIPCHECK(hipMemcpy(&ones, as<uint64_t>(d.sc_prefix) + e.uw, sizeof ones, hipMemcpyDeviceToHost));
+    if (ones != e.N) return RS_ERR_CORRUPT;
+  }
+  return RS_OK;
+}
+
+int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b,
+                 uint32_t flags, rs_mphf** out) {
+  const hipStream_t s = 0;
+  const uint64_t nb = n ? (n + b - 1) / b : 1;
+  const bool rotation = (flags & RS_FLAG_ROTATION) != 0;
+  Tables* T = nullptr;
+  int rc = tables_for(d, l, &T);
+  if (rc) return rc;
+
+  HIPCHECK(hipEventRecord(d.ev[0], s));
+  const Key* kin = reinterpret_cast<const Key*>(keys);
+  if (!(flags & RS_FLAG_KEYS_ON_DEVICE) && n) {
+    HIPCHECK(ensure(d.keys_in, n * sizeof(Key)));
+    HIPCHECK(hipMemcpy(d.keys_in.p, keys, n * sizeof(Key), hipMemcpyHostToDevice));
+    kin = as<Key>(d.keys_in);
+  }
+  HIPCHECK(ensure(d.k0, n * sizeof(Key)));
+  HIPCHECK(ensure(d.k1, n * sizeof(Key)));
+  HIPCHECK(ensure(d.cnt, nb * sizeof(uint32_t)));
+  HIPCHECK(ensure(d.fill, nb * sizeof(uint32_t)));
+  HIPCHECK(ensure(d.off, (nb + 1) * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.nodes, nb * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.node_base, (nb + 1) * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.len, nb * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.pos, (nb + 1) * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.tmp, scan_tmp_words(nb + 1) * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.ctl, sizeof(Control)));
+  Control* ctl = as<Control>(d.ctl);
+  HIPCHECK(hipEventRecord(d.ev[1], s));
+
+  // 1. buckets: sizes, borders, scatter, duplicate check
+  HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(ctl), sizeof(Control) / 8, 0, s));
+  HIPCHECK(fill_u32(as<uint32_t>(d.cnt), nb, 0, s));
+  HIPCHECK(fill_u32(as<uint32_t>(d.fill), nb, 0, s));
+  HIPCHECK(bucket_histogram(kin, n, nb, as<uint32_t>(d.cnt), ctl, s));
+  HIPCHECK(scan_excl_u32(as<uint32_t>(d.cnt), nb, as<uint64_t>(d.off), as<uint64_t>(d.tmp), s));
+  HIPCHECK(bucket_scatter(kin, n, nb, as<uint64_t>(d.off), as<uint32_t>(d.fill), as<Key>(d.k0), s));
+  Control h_ctl;
+  HIPCHECK(hipMemcpy(&h_ctl, ctl, sizeof h_ctl, hipMemcpyDeviceToHost));
+  if (h_ctl.maxm > kMaxBucketKeys) return RS_ERR_UNSUPPORTED;
+  const uint32_t maxm = h_ctl.maxm;
+  {
+    uint32_t p2 = 1;
+    while (p2 < maxm) p2 <<= 1;
+    // LDS of the duplicate check (next power of two) and of the search stage
+    if ((uint64_t)p2 * 8 + 1024 > (uint64_t)d.lds_per_block) return RS_ERR_UNSUPPORTED;
+  }
+  HIPCHECK(duplicate_check(as<Key>(d.k0), as<uint64_t>(d.off), nb, maxm, ctl, s));
+  HIPCHECK(node_counts(as<uint32_t>(d.cnt), nb, T->nodecnt, as<uint64_t>(d.nodes), s));
+  HIPCHECK(scan_excl_u64(as<uint64_t>(d.nodes), nb, as<uint64_t>(d.node_base), as<uint64_t>(d.tmp), s));
+  uint64_t total = 0;
+  HIPCHECK(hipMemcpy(&total, as<uint64_t>(d.node_base) + nb, sizeof total, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(&h_ctl, ctl, sizeof h_ctl, hipMemcpyDeviceToHost));
+  if (h_ctl.error) return -(int)h_ctl.error;
+  if (total >= (1ull << 31)) return RS_ERR_UNSUPPORTED;
+  HIPCHECK(hipEventRecord(d.ev[2], s));
+
+  // 2. seed search over all nodes
+  HIPCHECK(ensure(d.vals, total * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.msz, total * sizeof(uint32_t)));
+  uint32_t workers = 0;
+  if (total) {
+    HIPCHECK(ensure(d.tasks, total * sizeof(Task)));
+    HIPCHECK(ensure(d.states, total * sizeof(TaskState)));
+    HIPCHECK(ensure(d.ready_f, total * sizeof(uint32_t)));
+    const uint32_t lds = (maxm < 64 ? 64 : maxm) * sizeof(uint64_t);
+    int per_cu = 0;
+    HIPCHECK(search_occupancy(lds, &per_cu));
+    if (per_cu < 1) per_cu = 1;
+    workers = (uint32_t)per_cu * (uint32_t)d.cus;
+    if (const char* ew = getenv("RS_WORKERS")) {
+      const int w = atoi(ew);
+      if (w > 0 && (uint32_t)w < workers) workers = (uint32_t)w;
+    }
+    HIPCHECK(ensure(d.active, workers * sizeof(int32_t)));
+    HIPCHECK(ensure(d.jobs, sizeof(JobDev)));
+    HIPCHECK(fill_u64(as<uint64_t>(d.states), total * sizeof(TaskState) / 8, 0, s));
+    HIPCHECK(fill_u32(as<uint32_t>(d.ready_f), total, 0, s));
+    HIPCHECK(fill_u32(as<uint32_t>(d.active), workers, 0xFFFFFFFFu, s));
+    HIPCHECK(init_states(as<TaskState>(d.states), total, s));
+    HIPCHECK(hipMemcpy(&ctl->total, &total, sizeof(uint64_t), hipMemcpyHostToDevice));
+    JobDev job;
+    job.keys[0] = as<Key>(d.k0);
+    job.keys[1] = as<Key>(d.k1);
+    job.vals = as<uint64_t>(d.vals);
+    job.msz = as<uint32_t>(d.msz);
+    job.nodecnt = T->nodecnt;
+    job.tau = T->tau;
+    const Shape sh = make_shape(l);
+    job.l = sh.l;
+    job.la = sh.la;
+    job.ua = sh.ua;
+    job.rotation = rotation ? 1u : 0u;
+    HIPCHECK(hipMemcpy(d.jobs.p, &job, sizeof job, hipMemcpyHostToDevice));
+    HIPCHECK(queue_roots(as<uint32_t>(d.cnt), as<uint64_t>(d.off), as<uint64_t>(d.node_base), nb, 0,
+                         0, 0, as<Task>(d.tasks), as<uint32_t>(d.ready_f), ctl, s));
+    SearchParams P;
+    P.jobs = as<JobDev>(d.jobs);
+    P.tasks = as<Task>(d.tasks);
+    P.states = as<TaskState>(d.states);
+    P.ready = as<uint32_t>(d.ready_f);
+    P.active = as<int32_t>(d.active);
+    P.ctl = ctl;
+    P.start = d.start;
+    P.workers = workers;
+    P.stage_cap = maxm;
+    const char* e1 = getenv("RS_ROUNDS_LEAF");
+    const char* e2 = getenv("RS_ROUNDS_SPLIT");
+    P.rounds_leaf = e1 ? (uint32_t)atoi(e1) : 4u;
+    P.rounds_split = e2 ? (uint32_t)atoi(e2) : 8u;
+    if (P.rounds_leaf < 1) P.rounds_leaf = 1;
+    if (P.rounds_split < 1) P.rounds_split = 1;
+    P.cap_shift = 10;
+    P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
+    HIPCHECK(hipEventRecord(d.ev[3], s));
+    HIPCHECK(launch_search(P, workers, lds, s));
+  } else {
+    HIPCHECK(hipEventRecord(d.ev[3], s));
+  }
+  HIPCHECK(hipEventRecord(d.ev[4], s));
+  HIPCHECK(hipMemcpy(&h_ctl, ctl, sizeof h_ctl, hipMemcpyDeviceToHost));
+  if (h_ctl.error && getenv("RS_DEBUG")) {
+    fprintf(stderr,
+            "[rs debug] error %u: node %llu slot %llu m %u depth %u key_off %llu np %016llx "
+            "best %llu chunk %llu finished %llu/%llu head %llu tail %llu\n",
+            h_ctl.error, (unsigned long long)h_ctl.dbg_node, (unsigned long long)h_ctl.dbg_slot,
+            h_ctl.dbg_m, h_ctl.dbg_depth, (unsigned long long)h_ctl.dbg_key_off,
+            (unsigned long long)h_ctl.dbg_np, (unsigned long long)h_ctl.dbg_best,
+            (unsigned long long)h_ctl.dbg_chunk, (unsigned long long)h_ctl.finished,
+            (unsigned long long)total, (unsigned long long)h_ctl.head, (unsigned long long)h_ctl.tail);
+    if (h_ctl.dbg_m && h_ctl.dbg_m <= kMaxBucketKeys && h_ctl.dbg_key_off + h_ctl.dbg_m <= n) {
+      std::vector<Key> hk(h_ctl.dbg_m);
+      const Key* src = (h_ctl.dbg_depth & 1) ? as<Key>(d.k1) : as<Key>(d.k0);
+      if (hipMemcpy(hk.data(), src + h_ctl.dbg_key_off, h_ctl.dbg_m * sizeof(Key),
+                    hipMemcpyDeviceToHost) == hipSuccess)
+        for (uint32_t i = 0; i < h_ctl.dbg_m; ++i)
+          fprintf(stderr, "[rs debug] key %u %016llx %016llx\n", i, (unsigned long long)hk[i].w0,
+                  (unsigned long long)hk[i].w1);
+    }
+  }
+  if (h_ctl.error) return -(int)h_ctl.error;
+  if (h_ctl.finished != total) return RS_ERR_DEVICE;
+
+  // 3. encode: record lengths, offsets P_j, then bits
+  if (total == 0) HIPCHECK(fill_u64(as<uint64_t>(d.len), nb, 0, s));
+  else
+    HIPCHECK(gr_lengths(as<uint64_t>(d.node_base), nb, as<uint64_t>(d.vals), as<uint32_t>(d.msz),
+                        T->tau, as<uint64_t>(d.len), s));
+  HIPCHECK(scan_excl_u64(as<uint64_t>(d.len), nb, as<uint64_t>(d.pos), as<uint64_t>(d.tmp), s));
+  uint64_t gr_bits = 0;
+  HIPCHECK(hipMemcpy(&gr_bits, as<uint64_t>(d.pos) + nb, sizeof gr_bits, hipMemcpyDeviceToHost));
+
+  rs_mphf* f = new (std::nothrow) rs_mphf();
+  if (!f) return RS_ERR_OOM;
+  f->n = n;
+  f->nb = nb;
+  f->l = l;
+  f->b = b;
+  f->rotation = rotation ? 1u : 0u;
+  f->device = d.id;
+  f->efc = ef_layout(nb + 1, n, kHeaderWords);
+  f->efp = ef_layout(nb + 1, gr_bits, f->efc.at + f->efc.words());
+  f->gr_at = f->efp.at + f->efp.words();
+  f->gr_bits = gr_bits;
+  f->gr_words = (gr_bits + 63) / 64;
+  const uint64_t nw = f->gr_at + 2 + f->gr_words;
+  hipError_t he = hipMalloc(&f->d_words, nw * sizeof(uint64_t));
+  if (he != hipSuccess) {
+    release(f);
+    return from_hip(he);
+  }
+  auto fail = [&](int code) {
+    release(f);
+    return code;
+  };
+  if (fill_u64(f->d_words, nw, 0, s) != hipSuccess) return fail(RS_ERR_DEVICE);
+  std::vector<uint64_t> hdr;
+  hdr.push_back(kMagic);
+  hdr.push_back(kVersion | ((uint64_t)f->rotation << 32));
+  hdr.push_back(n);
+  hdr.push_back((uint64_t)l | ((uint64_t)b << 32));
+  hdr.push_back(nb);
+  const EFLayout* efs[2] = {&f->efc, &f->efp};
+  for (int i = 0; i < 2; ++i) {
+    const EFLayout& e = *efs[i];
+    const uint64_t eh[6] = {e.N, e.U, e.L, e.lw, e.ub, e.uw};
+    if (hipMemcpy(f->d_words + e.at, eh, sizeof eh, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RS_ERR_DEVICE);
+  }
+  const uint64_t gh[2] = {gr_bits, f->gr_words};
+  if (hipMemcpy(f->d_words, hdr.data(), hdr.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f->d_words + f->gr_at, gh, sizeof gh, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RS_ERR_DEVICE);
+  uint64_t* gr = f->d_words + f->gr_at + 2;
+  if (total && gr_write(as<uint64_t>(d.node_base), nb, as<uint64_t>(d.vals), as<uint32_t>(d.msz),
+                        T->tau, as<uint64_t>(d.pos), gr, s) != hipSuccess)
+    return fail(RS_ERR_DEVICE);
+  const uint64_t* xs[2] = {as<uint64_t>(d.off), as<uint64_t>(d.pos)};
+  for (int i = 0; i < 2; ++i) {
+    const EFLayout& e = *efs[i];
+    if (ef_write(xs[i], e.N, (uint32_t)e.L, f->d_words + e.at + kEfHeaderWords,
+                 f->d_words + e.at + kEfHeaderWords + e.lw, s) != hipSuccess)
+      return fail(RS_ERR_DEVICE);
+  }
+  if (hipEventRecord(d.ev[5], s) != hipSuccess) return fail(RS_ERR_DEVICE);
+  f->words.resize(nw);
+  if (hipMemcpy(f->words.data(), f->d_words, nw * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(RS_ERR_DEVICE);
+  rc = attach_device(d, f, true);
+  if (rc) return fail(rc);
+
+  if (flags & RS_FLAG_KEEP_VALUES) {
+    f->keep_vals.resize(total);
+    f->keep_base.resize(nb + 1);
+    if ((total && hipMemcpy(f->keep_vals.data(), d.vals.p, total * 8, hipMemcpyDeviceToHost) != hipSuccess) ||
+        hipMemcpy(f->keep_base.data(), d.node_base.p, (nb + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(RS_ERR_DEVICE);
+  }
+  rs_stats& st = f->stats;
+  memset(&st, 0, sizeof st);
+  st.n = n;
+  st.nb = nb;
+  st.nodes = total;
+  st.split_nodes = h_ctl.splits;
+  st.leaf_nodes = h_ctl.leaves;
+  st.useful_evals_split = h_ctl.evals_split;
+  st.useful_evals_leaf = h_ctl.evals_leaf;
+  st.gr_bits = gr_bits;
+  st.bytes = nw * 8;
+  st.max_bucket = maxm;
+  st.workers = workers;
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, d.ev[1], d.ev[2]);
+  st.ms_sort = ms;
+  (void)hipEventElapsedTime(&ms, d.ev[3], d.ev[4]);
+  st.ms_search = ms;
+  (void)hipEventElapsedTime(&ms, d.ev[4], d.ev[5]);
+  st.ms_encode = ms;
+  (void)hipEventElapsedTime(&ms, d.ev[0], d.ev[5]);
+  st.ms_total = ms;
+  *out = f;
+  return RS_OK;
+}
+
+int parse(const uint64_t* w, uint64_t nw, rs_mphf* f) {
+  if (nw < kHeaderWords || w[0] != kMagic || (w[1] & 0xFFFFFFFFull) != kVersion) return RS_ERR_CORRUPT;
+  f->rotation = (uint32_t)((w[1] >> 32) & 1u);
+  if (w[1] >> 33) return RS_ERR_CORRUPT;
+  f->n = w[2];
+  f->l = (uint32_t)(w[3] & 0xFFFFFFFFull);
+  f->b = (uint32_t)(w[3] >> 32);
+  f->nb = w[4];
+  if (f->l < 2 || f->l > kMaxLeaf || f->b < 1 || f->b > RS_MAX_BUCKET_SIZE || f->n >= (1ull << 40))
+    return RS_ERR_CORRUPT;
+  const uint64_t nb = f->n ? (f->n + f->b - 1) / f->b : 1;
+  if (f->nb != nb) return RS_ERR_CORRUPT;
+  uint64_t at = kHeaderWords;
+  EFLayout* efs[2] = {&f->efc, &f->efp};
+  for (int i = 0; i < 2; ++i) {
+    if (nw - at < kEfHeaderWords) return RS_ERR_CORRUPT;
+    const uint64_t* h = w + at;
+    if (h[0] != nb + 1 || h[2] > 63) return RS_ERR_CORRUPT;
+    EFLayout e = ef_layout(h[0], h[1], at);
+    if (e.L != h[2] || e.lw != h[3] || e.ub != h[4] || e.uw != h[5]) return RS_ERR_CORRUPT;
+    if (nw - at < e.words()) return RS_ERR_CORRUPT;
+    *efs[i] = e;
+    at += e.words();
+  }
+  if (f->efc.U != f->n) return RS_ERR_CORRUPT;
+  if (nw - at < 2) return RS_ERR_CORRUPT;
+  f->gr_at = at;
+  f->gr_bits = w[at];
+  f->gr_words = w[at + 1];
+  if (f->gr_words != (f->gr_bits + 63) / 64 || nw - at - 2 != f->gr_words) return RS_ERR_CORRUPT;
+  if (f->efp.U != f->gr_bits) return RS_ERR_CORRUPT;
+  return RS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rs_build(const rs_key128* keys, uint64_t n, uint32_t leaf_size, uint32_t bucket_size,
+             uint32_t flags, rs_mphf** out) {
+  if (!out) return RS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (leaf_size < 2 || leaf_size > kMaxLeaf || bucket_size < 1 || bucket_size > RS_MAX_BUCKET_SIZE ||
+      n >= (1ull << 40) || (n && !keys) ||
+      (flags & ~(uint32_t)(RS_FLAG_ROTATION | RS_FLAG_KEYS_ON_DEVICE | RS_FLAG_KEEP_VALUES)))
+    return RS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Device* d = nullptr;
+  int rc = device_init(&d);
+  if (rc) return rc;
+  rc = build_locked(*d, keys, n, leaf_size, bucket_size, flags, out);
+  if (rc) {
+    // leave the device usable for the next call
+    (void)hipDeviceSynchronize();
+    (void)hipGetLastError();
+  }
+  return rc;
+}
+
+int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out, uint32_t flags) {
+  if (!f || (n && (!keys || !out)) || (flags & ~(uint32_t)RS_FLAG_KEYS_ON_DEVICE))
+    return RS_ERR_INVALID_ARG;
+  if (!n) return RS_OK;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Device* d = nullptr;
+  int rc = device_init(&d);
+  if (rc) return rc;
+  Tables* T = nullptr;
+  rc = tables_for(*d, f->l, &T);
+  if (rc) return rc;
+  const Key* kd = reinterpret_cast<const Key*>(keys);
+  uint64_t* od = out;
+  const bool on_dev = (flags & RS_FLAG_KEYS_ON_DEVICE) != 0;
+  if (!on_dev) {
+    HIPCHECK(ensure(d->qkeys, n * sizeof(Key)));
+    HIPCHECK(ensure(d->qout, n * sizeof(uint64_t)));
+    HIPCHECK(hipMemcpy(d->qkeys.p, keys, n * sizeof(Key), hipMemcpyHostToDevice));
+    kd = as<Key>(d->qkeys);
+    od = as<uint64_t>(d->qout);
+  }
+  QueryParams q;
+  q.C.lower = f->d_words + f->efc.at + kEfHeaderWords;
+  q.C.upper = q.C.lower + f->efc.lw;
+  q.C.samples = f->d_samples;
+  q.C.N = f->efc.N;
+  q.C.L = (uint32_t)f->efc.L;
+  q.P.lower = f->d_words + f->efp.at + kEfHeaderWords;
+  q.P.upper = q.P.lower + f->efp.lw;
+  q.P.samples = f->d_samples + f->ns_c;
+  q.P.N = f->efp.N;
+  q.P.L = (uint32_t)f->efp.L;
+  q.gr = f->d_words + f->gr_at + 2;
+  q.gr_bits = f->gr_bits;
+  q.nb = f->nb;
+  q.shape = make_shape(f->l);
+  q.rotation = f->rotation;
+  q.nodecnt = T->nodecnt;
+  q.fixedbits = T->fixedbits;
+  q.tau = T->tau;
+  q.start = d->start;
+  HIPCHECK(launch_query(q, kd, n, od, 0));
+  if (!on_dev) HIPCHECK(hipMemcpy(out, od, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  else HIPCHECK(hipStreamSynchronize(0));
+  return RS_OK;
+}
+
+int rs_serialize(const rs_mphf* f, const uint8_t** bytes, uint64_t* nbytes) {
+  if (!f || !bytes || !nbytes) return RS_ERR_INVALID_ARG;
+  *bytes = reinterpret_cast<const uint8_t*>(f->words.data());
+  *nbytes = f->words.size() * sizeof(uint64_t);
+  return RS_OK;
+}
+
+int rs_deserialize(const uint8_t* bytes, uint64_t nbytes, rs_mphf** out) {
+  if (!out || (!bytes && nbytes)) return RS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (nbytes % 8) return RS_ERR_CORRUPT;
+  rs_mphf* f = new (std::nothrow) rs_mphf();
+  if (!f) return RS_ERR_OOM;
+  f->words.resize(nbytes / 8);
+  if (nbytes) memcpy(f->words.data(), bytes, nbytes);
+  int rc = parse(f->words.data(), f->words.size(), f);
+  if (rc) {
+    release(f);
+    return rc;
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  Device* d = nullptr;
+  rc = device_init(&d);
+  if (!rc) rc = attach_device(*d, f, false);
+  if (rc) {
+    release(f);
+    return rc;
+  }
+  f->device = d->id;
+  f->stats.n = f->n;
+  f->stats.nb = f->nb;
+  f->stats.gr_bits = f->gr_bits;
+  f->stats.bytes = nbytes;
+  *out = f;
+  return RS_OK;
+}
+
+int rs_debug_node_values(const rs_mphf* f, uint64_t bucket, uint64_t* vals, uint64_t cap,
+                         uint64_t* count) {
+  if (!f || !count || f->keep_base.empty() || bucket >= f->nb) return RS_ERR_INVALID_ARG;
+  const uint64_t b = f->keep_base[bucket], e = f->keep_base[bucket + 1];
+  *count = e - b;
+  if (e - b > cap || (e > b && !vals)) return RS_ERR_INVALID_ARG;
+  for (uint64_t i = b; i < e; ++i) vals[i - b] = f->keep_vals[i];
+  return RS_OK;
+}
+
+int rs_get_stats(const rs_mphf* f, rs_stats* st) {
+  if (!f || !st) return RS_ERR_INVALID_ARG;
+  *st = f->stats;
+  return RS_OK;
+}
+
+void rs_free(rs_mphf* f) { release(f); }
+
+const char* rs_strerror(int code) {
+  switch (code) {
+    case RS_OK: return "ok";
+    case RS_ERR_INVALID_ARG: return "invalid argument";
+    case RS_ERR_DUPLICATE: return "two keys of one bucket share their hashed word";
+    case RS_ERR_OOM: return "out of memory";
+    case RS_ERR_DEVICE: return "HIP device error";
+    case RS_ERR_CORRUPT: return "corrupt serialised data";
+    case RS_ERR_SEARCH_LIMIT: return "seed search limit reached";
+    case RS_ERR_UNSUPPORTED: return "bucket larger than supported";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

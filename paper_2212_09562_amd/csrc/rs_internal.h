@@ -1,0 +1,164 @@
+// Internal definitions of the MI355X RecSplit library: tree shape, hash,
+// device work-queue records.  Shared by the host orchestration and the HIP
+// kernels of this library only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/recsplit.h"
+
+namespace rs {
+
+constexpr uint32_t kMaxLeaf = RS_MAX_LEAF_SIZE;
+constexpr uint32_t kMaxBucketKeys = RS_MAX_BUCKET_KEYS;
+constexpr uint32_t kTable = kMaxBucketKeys + 1;  // per-size tables cover m = 0..kMaxBucketKeys
+constexpr uint32_t kMaxDepth = 64;
+constexpr uint32_t kMaxParts = 16;  // fanout never exceeds 9 for l <= 24
+constexpr uint64_t kInf = ~0ull;
+constexpr uint32_t kWG = 256;  // threads per search worker (4 wave64)
+constexpr uint32_t kWaves = kWG / 64;
+
+enum Kind : uint32_t { kNone = 0, kLeaf = 1, kLower = 2, kUpper = 3, kBinary = 4 };
+
+// Splitting-tree shape (Sec. 2.2): leaf size l; lower aggregation unit
+// la = l * lower fanout; upper aggregation unit ua = la * upper fanout.
+struct Shape {
+  uint32_t l, la, ua;
+};
+
+// Fanouts of the two levels above the leaves, max{2, ceil(0.35 l + 0.55)} and
+// max{2, ceil(0.21 l + 0.9)}, evaluated exactly as ceil((35l+55)/100) and
+// ceil((21l+90)/100).
+inline Shape make_shape(uint32_t l) {
+  uint32_t lo = (35u * l + 154u) / 100u;
+  uint32_t up = (21u * l + 189u) / 100u;
+  if (lo < 2) lo = 2;
+  if (up < 2) up = 2;
+  Shape s;
+  s.l = l;
+  s.la = lo * l;
+  s.ua = up * s.la;
+  return s;
+}
+
+__host__ __device__ inline uint32_t kind_of(const Shape& s, uint32_t m) {
+  return m <= 1 ? kNone : m <= s.l ? kLeaf : m <= s.la ? kLower : m <= s.ua ? kUpper : kBinary;
+}
+
+// Children of an inner node.  Lower/upper nodes: ceil(m/unit) parts of size
+// unit, the last taking the remainder.  Fanout-2 nodes: the left child gets
+// the smallest multiple of ua not below floor(m/2), the right the rest.
+struct Parts {
+  uint32_t k;     // number of children
+  uint32_t unit;  // size of every child but the last (the left size for fanout 2)
+  uint32_t last;  // size of the last child
+};
+
+__host__ __device__ inline Parts parts_of(const Shape& s, uint32_t m) {
+  Parts p;
+  uint32_t kd = kind_of(s, m);
+  if (kd == kLower || kd == kUpper) {
+    uint32_t u = kd == kLower ? s.l : s.la;
+    p.k = (m + u - 1) / u;
+    p.unit = u;
+    p.last = m - (p.k - 1) * u;
+  } else if (kd == kBinary) {
+    uint32_t half = m / 2;
+    p.k = 2;
+    p.unit = s.ua * ((half + s.ua - 1) / s.ua);
+    p.last = m - p.unit;
+  } else {
+    p.k = 0;
+    p.unit = 0;
+    p.last = 0;
+  }
+  return p;
+}
+
+__host__ __device__ inline uint32_t part_size(const Parts& p, uint32_t j) {
+  return j + 1 < p.k ? p.unit : p.last;
+}
+
+// Hash of a key word w1 under identifier x: the SplitMix64 output mixer of
+// (w1 + x) mod 2^64 (Steele, Lea, Flood 2014).  Only the top 32 bits are ever
+// used (positions are multiply-high reductions of them), so the device form
+// returns just those.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t hash_top(uint64_t w1, uint64_t x) {
+  uint64_t z = w1 + x;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  uint32_t h = (uint32_t)(z >> 32);
+  return h ^ (h >> 31);
+}
+
+// floor(h * M / 2^32) for the top word h of a hash.
+__device__ __forceinline__ uint32_t reduce(uint32_t h, uint32_t M) { return __umulhi(h, M); }
+
+// Work records of the device scheduler.
+struct Key {
+  uint64_t w0, w1;
+};
+
+struct Task {
+  uint64_t key_off;  // first key of the node in the job's work arrays
+  uint64_t node;     // index of the node's value (job-relative, preorder per bucket)
+  uint32_t m;        // keys in the node
+  uint16_t depth;    // depth in its bucket tree (root 0)
+  uint16_t job;
+};
+
+struct TaskState {
+  uint64_t np;    // next chunk index (high 32 bits) and chunks in flight (low 32)
+  uint64_t best;  // smallest valid value found so far (kInf: none)
+  uint32_t closed;
+  uint32_t pad0;
+  uint64_t pad1;
+};
+
+struct JobDev {
+  Key* keys[2];             // ping-pong key arrays: depth d reads keys[d & 1]
+  uint64_t* vals;           // node values
+  uint32_t* msz;            // node sizes
+  const uint32_t* nodecnt;  // stored nodes of a subtree of size m
+  const uint8_t* tau;       // Rice parameter of a node of size m
+  uint32_t l, la, ua;
+  uint32_t rotation;
+};
+
+struct Control {
+  uint64_t head;      // next queue slot to hand out
+  uint64_t tail;      // next queue slot to fill
+  uint64_t finished;  // nodes whose value is final
+  uint64_t total;     // nodes of all jobs
+  uint32_t error;     // first RS_ERR_* seen by a kernel (as a positive number)
+  uint32_t maxm;      // largest bucket
+  uint64_t evals_split, evals_leaf;  // useful hash evaluations
+  uint64_t splits, leaves;
+  // the node that raised the first error (diagnostics)
+  uint64_t dbg_key_off, dbg_node, dbg_slot, dbg_np, dbg_best, dbg_chunk;
+  uint32_t dbg_m, dbg_depth;
+};
+
+struct SearchParams {
+  const JobDev* jobs;
+  Task* tasks;
+  TaskState* states;
+  uint32_t* ready;
+  int32_t* active;  // queue slot owned by each worker, -1 when none
+  Control* ctl;
+  const uint64_t* start;  // starting seed per depth
+  uint32_t workers;
+  uint32_t stage_cap;  // keys staged in LDS per worker
+  uint32_t rounds_leaf, rounds_split;
+  uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
+  uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
+};
+
+}  // namespace rs

@@ -1,0 +1,70 @@
+// Host-side launchers of the library's kernels (one translation unit each).
+#pragma once
+
+#include "rs_internal.h"
+
+namespace rs {
+
+hipError_t fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+
+// Exclusive scan: out[0..n] with out[n] the total; tmp needs scan_tmp_words(n) words.
+uint64_t scan_tmp_words(uint64_t n);
+hipError_t scan_excl_u32(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
+hipError_t scan_excl_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
+
+hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, Control* ctl,
+                            hipStream_t s);
+hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
+                          uint32_t* fill, Key* out, hipStream_t s);
+hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t maxm,
+                           Control* ctl, hipStream_t s);
+hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s);
+hipError_t node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* nodecnt, uint64_t* out,
+                       hipStream_t s);
+hipError_t queue_roots(const uint32_t* cnt, const uint64_t* off, const uint64_t* node_base,
+                       uint64_t nb, uint32_t job, uint64_t key_base, uint64_t node_off, Task* tasks,
+                       uint32_t* ready, Control* ctl, hipStream_t s);
+
+// Seed search (persistent kernel).
+hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
+
+// Encoding.
+hipError_t gr_lengths(const uint64_t* node_base, uint64_t nb, const uint64_t* vals,
+                      const uint32_t* msz, const uint8_t* tau, uint64_t* len, hipStream_t s);
+hipError_t gr_write(const uint64_t* node_base, uint64_t nb, const uint64_t* vals, const uint32_t* msz,
+                    const uint8_t* tau, const uint64_t* pos, uint64_t* gr, hipStream_t s);
+hipError_t ef_write(const uint64_t* x, uint64_t N, uint32_t L, uint64_t* lower, uint64_t* upper,
+                    hipStream_t s);
+
+// Select support: every 256th one of a bit vector.
+hipError_t select_samples(const uint64_t* words, uint64_t nwords, uint64_t* scratch_counts,
+                          uint64_t* scratch_prefix, uint64_t* scan_tmp, uint64_t* samples,
+                          uint64_t nsamples, hipStream_t s);
+
+struct EFView {
+  const uint64_t* lower;
+  const uint64_t* upper;
+  const uint64_t* samples;
+  uint64_t N;
+  uint32_t L;
+};
+
+struct QueryParams {
+  EFView C, P;
+  const uint64_t* gr;
+  uint64_t gr_bits;
+  uint64_t nb;
+  Shape shape;
+  uint32_t rotation;
+  const uint32_t* nodecnt;
+  const uint32_t* fixedbits;
+  const uint8_t* tau;
+  const uint64_t* start;
+};
+
+hipError_t launch_query(const QueryParams& q, const Key* keys, uint64_t n, uint64_t* out,
+                        hipStream_t s);
+
+}  // namespace rs

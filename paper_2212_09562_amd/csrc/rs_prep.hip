@@ -1,0 +1,312 @@
+// Bucketing (Sec. 2.2: keys to buckets of expected size b, sorted by bucket,
+// bucket borders), device-wide exclusive scans, the duplicate check, and the
+// roots of the search queue.
+#include "rs_launch.h"
+
+namespace rs {
+
+namespace {
+
+constexpr uint32_t kScanThreads = 256;
+constexpr uint32_t kScanPer = 4;
+constexpr uint32_t kScanBlock = kScanThreads * kScanPer;
+
+__device__ __forceinline__ uint64_t bucket_of(uint64_t w0, uint64_t nb) { return __umul64hi(w0, nb); }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const uint32_t lane = __lane_id();
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    T o = __shfl_up(v, d);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan of the 1024 values of one block; returns the block total.
+__device__ uint64_t block_excl_scan(uint64_t (&v)[kScanPer], uint64_t* s_wave) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t sum = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPer; ++i) sum += v[i];
+  uint64_t incl = wave_incl_scan(sum);
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  uint64_t wbase = 0, total = 0;
+  for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) wbase += s_wave[w];
+    total += s_wave[w];
+  }
+  uint64_t run = wbase + incl - sum;
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPer; ++i) {
+    uint64_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(const T* in, uint64_t n, uint64_t* sums) {
+  __shared__ uint64_t s_wave[kScanThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+  uint64_t v[kScanPer];
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPer; ++i) v[i] = base + i < n ? (uint64_t)in[base + i] : 0;
+  uint64_t total = block_excl_scan(v, s_wave);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block scans the per-block sums in place (exclusive), in slices of 1024.
+__global__ void __launch_bounds__(kScanThreads) k_scan_top(uint64_t* sums, uint64_t nblocks) {
+  __shared__ uint64_t s_wave[kScanThreads / 64];
+  uint64_t carry = 0;
+  for (uint64_t s0 = 0; s0 < nblocks; s0 += kScanBlock) {
+    const uint64_t base = s0 + threadIdx.x * kScanPer;
+    uint64_t v[kScanPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kScanPer; ++i) v[i] = base + i < nblocks ? sums[base + i] : 0;
+    uint64_t total = block_excl_scan(v, s_wave);
+#pragma unroll
+    for (uint32_t i = 0; i < kScanPer; ++i)
+      if (base + i < nblocks) sums[base + i] = v[i] + carry;
+    carry += total;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_out(const T* in, uint64_t n,
+                                                          const uint64_t* sums, uint64_t* out) {
+  __shared__ uint64_t s_wave[kScanThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+  uint64_t v[kScanPer];
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPer; ++i) v[i] = base + i < n ? (uint64_t)in[base + i] : 0;
+  const uint64_t total = block_excl_scan(v, s_wave);
+  const uint64_t add = sums[blockIdx.x];
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPer; ++i)
+    if (base + i < n) out[base + i] = v[i] + add;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = add + total;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Bucket sizes.  With few buckets each block counts in LDS and flushes once.
+__global__ void k_hist(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, uint32_t use_lds) {
+  extern __shared__ uint32_t s_h[];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  if (use_lds) {
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+      atomicAdd(&s_h[bucket_of(keys[i].w0, nb)], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+      if (s_h[i]) atomicAdd(&cnt[i], s_h[i]);
+  } else {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+      atomicAdd(&cnt[bucket_of(keys[i].w0, nb)], 1u);
+  }
+}
+
+__global__ void k_max_bucket(const uint32_t* cnt, uint64_t nb, Control* ctl) {
+  uint32_t mx = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nb;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    mx = max(mx, cnt[i]);
+  for (uint32_t d = 32; d > 0; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d));
+  if ((threadIdx.x & 63) == 0) atomicMax(&ctl->maxm, mx);
+}
+
+__global__ void k_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
+                          uint32_t* fill, Key* out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const Key k = keys[i];
+    const uint64_t b = bucket_of(k.w0, nb);
+    out[off[b] + atomicAdd(&fill[b], 1u)] = k;
+  }
+}
+
+// Two keys of a bucket with equal w1 hash alike under every seed, so their
+// leaf could never be a bijection: sort the bucket's w1 words (bitonic, in
+// LDS) and compare neighbours.
+__global__ void __launch_bounds__(256) k_dupcheck(const Key* keys, const uint64_t* off, uint64_t nb,
+                                                  Control* ctl) {
+  extern __shared__ uint64_t s[];
+  for (uint64_t j = blockIdx.x; j < nb; j += gridDim.x) {
+    const uint64_t o = off[j];
+    const uint32_t m = (uint32_t)(off[j + 1] - o);
+    if (m < 2) continue;
+    uint32_t p2 = 1;
+    while (p2 < m) p2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) s[i] = i < m ? keys[o + i].w1 : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= p2; k <<= 1) {
+      for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+        for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+          const uint32_t x = i ^ d;
+          if (x > i) {
+            const uint64_t a = s[i], b = s[x];
+            const bool up = (i & k) == 0;
+            if ((a > b) == up) {
+              s[i] = b;
+              s[x] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    bool dup = false;
+    for (uint32_t i = threadIdx.x; i + 1 < m; i += blockDim.x) dup |= s[i] == s[i + 1];
+    if (dup) atomicCAS(&ctl->error, 0u, (uint32_t)(-RS_ERR_DUPLICATE));
+    __syncthreads();
+  }
+}
+
+__global__ void k_init_states(TaskState* st, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    TaskState t;
+    t.np = 0;
+    t.best = kInf;
+    t.closed = 0;
+    t.pad0 = 0;
+    t.pad1 = 0;
+    st[i] = t;
+  }
+}
+
+__global__ void k_node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* nodecnt,
+                              uint64_t* out) {
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nb;
+       j += (uint64_t)gridDim.x * blockDim.x)
+    out[j] = nodecnt[cnt[j]];
+}
+
+__global__ void k_roots(const uint32_t* cnt, const uint64_t* off, const uint64_t* node_base,
+                        uint64_t nb, uint32_t job, uint64_t key_base, uint64_t node_off,
+                        Task* tasks, uint32_t* ready, Control* ctl) {
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nb;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t m = cnt[j];
+    if (m < 2) continue;
+    const uint64_t slot = __hip_atomic_fetch_add(&ctl->tail, 1ull, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    Task t;
+    t.key_off = key_base + off[j];
+    t.node = node_off + node_base[j];
+    t.m = m;
+    t.depth = 0;
+    t.job = (uint16_t)job;
+    tasks[slot] = t;
+    __hip_atomic_store(&ready[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
+  uint64_t g = (n + threads - 1) / threads;
+  if (g > cap) g = cap;
+  return g ? (uint32_t)g : 1u;
+}
+
+}  // namespace
+
+hipError_t fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_fill_u64<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_fill_u32<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+uint64_t scan_tmp_words(uint64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+template <typename T>
+static hipError_t scan_impl(const T* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s) {
+  if (n == 0) return fill_u64(out, 1, 0, s);
+  const uint64_t nblocks = (n + kScanBlock - 1) / kScanBlock;
+  k_scan_sums<T><<<(uint32_t)nblocks, kScanThreads, 0, s>>>(in, n, tmp);
+  k_scan_top<<<1, kScanThreads, 0, s>>>(tmp, nblocks);
+  k_scan_out<T><<<(uint32_t)nblocks, kScanThreads, 0, s>>>(in, n, tmp, out);
+  return hipGetLastError();
+}
+
+hipError_t scan_excl_u32(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tmp,
+                         hipStream_t s) {
+  return scan_impl<uint32_t>(in, n, out, tmp, s);
+}
+
+hipError_t scan_excl_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* tmp,
+                         hipStream_t s) {
+  return scan_impl<uint64_t>(in, n, out, tmp, s);
+}
+
+hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, Control* ctl,
+                            hipStream_t s) {
+  if (n) {
+    const bool lds = nb <= 16384;
+    const uint32_t grid = grid_for(n, 256 * 16, lds ? 512 : 8192);
+    k_hist<<<grid, 256, lds ? (uint32_t)(nb * sizeof(uint32_t)) : 0, s>>>(keys, n, nb, cnt,
+                                                                          lds ? 1u : 0u);
+  }
+  k_max_bucket<<<grid_for(nb, 256, 1024), 256, 0, s>>>(cnt, nb, ctl);
+  return hipGetLastError();
+}
+
+hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
+                          uint32_t* fill, Key* out, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_scatter<<<grid_for(n, 256, 16384), 256, 0, s>>>(keys, n, nb, off, fill, out);
+  return hipGetLastError();
+}
+
+hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t maxm,
+                           Control* ctl, hipStream_t s) {
+  if (maxm < 2) return hipSuccess;
+  uint32_t p2 = 1;
+  while (p2 < maxm) p2 <<= 1;
+  k_dupcheck<<<grid_for(nb, 1, 4096), 256, p2 * sizeof(uint64_t), s>>>(keys, off, nb, ctl);
+  return hipGetLastError();
+}
+
+hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_init_states<<<grid_for(n, 256, 4096), 256, 0, s>>>(st, n);
+  return hipGetLastError();
+}
+
+hipError_t node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* nodecnt, uint64_t* out,
+                       hipStream_t s) {
+  k_node_counts<<<grid_for(nb, 256, 4096), 256, 0, s>>>(cnt, nb, nodecnt, out);
+  return hipGetLastError();
+}
+
+hipError_t queue_roots(const uint32_t* cnt, const uint64_t* off, const uint64_t* node_base,
+                       uint64_t nb, uint32_t job, uint64_t key_base, uint64_t node_off, Task* tasks,
+                       uint32_t* ready, Control* ctl, hipStream_t s) {
+  k_roots<<<grid_for(nb, 256, 4096), 256, 0, s>>>(cnt, off, node_base, nb, job, key_base,
+                                                  node_off, tasks, ready, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace rs

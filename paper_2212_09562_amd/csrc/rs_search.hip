@@ -1,0 +1,595 @@
+// Persistent seed-search kernel: every inner node's split seed and every
+// leaf's bijection value (Sec. 2.2 "Splitting Trees" and "Bijections",
+// Sec. 4 rotation fitting), for all buckets of one or more jobs, in one
+// launch.
+//
+// Scheduling.  Nodes are tasks of a device queue.  The roots of all buckets
+// are queued before the launch; a split that finishes redistributes its keys
+// into its children's ranges and queues them.  Each workgroup (4 wave64) is
+// a worker: it owns one task at a time, stages the task's keys in LDS and
+// tries seeds in chunks of rounds * 256 consecutive attempts, one attempt per
+// lane.  Chunks are claimed with one atomic on the task, so idle workers
+// join a running task (the tail of a geometric search is shared by the whole
+// GPU) and the smallest valid value is still exact: a chunk is evaluated
+// unless it starts above the best value already found, and the task closes
+// when no claimed chunk is left in flight.  Whoever drops the in-flight count
+// to zero with a value known finalizes the task.
+//
+// Minimality (Sec. 5.1: the stored number must be as small as possible):
+// within a round a wave takes the lowest lane whose attempt is valid (ballot
+// then count-trailing-zeros); across waves and chunks the minimum is taken
+// with atomicMin, and no chunk that could hold a smaller value is skipped.
+#include "rs_launch.h"
+
+namespace rs {
+
+namespace {
+
+constexpr uint64_t kStop = ~0ull;
+constexpr uint64_t kNoSlot = ~0ull;
+constexpr uint64_t kExhausted = ~0ull - 1;
+constexpr uint64_t kHelpAfter = 2;  // chunks a task must have used before others join it
+
+enum : uint32_t { kActExit = 0, kActOwn = 1, kActHelp = 2, kActScan = 3, kActRetry = 4 };
+
+template <typename T>
+__device__ __forceinline__ T ld_acquire(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_release(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool set_error(Control* ctl, uint32_t code) {
+  uint32_t expected = 0;
+  return __hip_atomic_compare_exchange_strong(&ctl->error, &expected, code, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void record_failure(Control* ctl, const Task& t, uint64_t slot, const TaskState* st,
+                               uint64_t chunk) {
+  ctl->dbg_key_off = t.key_off;
+  ctl->dbg_node = t.node;
+  ctl->dbg_slot = slot;
+  ctl->dbg_np = ld_relaxed(&st->np);
+  ctl->dbg_best = ld_relaxed(&st->best);
+  ctl->dbg_chunk = chunk;
+  ctl->dbg_m = t.m;
+  ctl->dbg_depth = t.depth;
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t mask_below(uint32_t lane) {
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Rotate the m low bits of x left by r (0 <= r < m <= 24).
+__device__ __forceinline__ uint32_t rot_m(uint32_t x, uint32_t r, uint32_t m, uint32_t full) {
+  return ((x << r) | (x >> (m - r))) & full;
+}
+
+// Everything a worker needs to know about its current task, wave-uniform.
+struct Node {
+  uint32_t kind, m, k, unit, last;
+  uint32_t F;       // bits per packed child counter
+  uint32_t target;  // packed expected counts
+  uint32_t thr;     // fanout 2: a key goes left iff its hash top word < thr
+  uint32_t magic;   // floor(p / unit) == (p * magic) >> 20 for p < m
+  uint32_t full;    // 1 when every child has exactly unit keys
+  uint32_t na;      // leaf keys of class A (staged first)
+  uint32_t mult;    // value per attempt: m for rotation leaves, else 1
+  uint32_t rotation;
+  uint32_t fullmask;
+  uint64_t start;
+  uint64_t cap;  // attempts after which the search is reported as failed
+};
+
+__device__ Node make_node(const Task& t, const JobDev& J, const uint64_t* start,
+                          uint32_t cap_shift) {
+  Node c;
+  Shape s;
+  s.l = uni(J.l);
+  s.la = uni(J.la);
+  s.ua = uni(J.ua);
+  c.m = uni(t.m);
+  c.kind = kind_of(s, c.m);
+  Parts p = parts_of(s, c.m);
+  c.k = p.k;
+  c.unit = p.unit;
+  c.last = p.last;
+  c.rotation = uni(J.rotation);
+  const uint32_t depth = uni(t.depth);
+  c.start = uni64(start[depth < kMaxDepth ? depth : kMaxDepth - 1]);
+  c.F = c.k ? 32u / c.k : 0;
+  c.full = (c.kind == kLower || c.kind == kUpper) && c.last == c.unit;
+  uint32_t tg = 0;
+  for (uint32_t j = 0; j < c.k; ++j) tg += part_size(p, j) << (c.F * j);
+  c.target = tg;
+  c.thr = 0;
+  if (c.kind == kBinary) c.thr = (uint32_t)((((uint64_t)c.unit << 32) + c.m - 1) / c.m);
+  c.magic = c.unit ? ((1u << 20) + c.unit - 1) / c.unit : 0;
+  c.mult = (c.kind == kLeaf && c.rotation) ? c.m : 1u;
+  c.fullmask = c.m >= 32 ? ~0u : ((1u << c.m) - 1u);
+  c.na = 0;
+  // tau is within 2 bits of log2 of the expected number of trials, so a
+  // node that runs past 2^(tau + cap_shift) attempts is a bug, not bad luck
+  uint32_t sh = uni((uint32_t)J.tau[c.m]) + cap_shift;
+  if (sh < 16) sh = 16;
+  if (sh > 40) sh = 40;
+  c.cap = 1ull << sh;
+  return c;
+}
+
+// ---------------------------------------------------------------- rounds
+// Each returns the smallest valid value among the 64 attempts a0 .. a0+63 of
+// this wave (wave-uniform), or kInf.
+
+// Brute-force leaf: OR 2^position over all keys; valid when all m bits are set.
+__device__ __forceinline__ uint64_t round_leaf_brute(const uint64_t* keys, const Node& c,
+                                                      uint64_t a0) {
+  const uint64_t X = c.start + a0 + lane_id();
+  uint32_t mask = 0;
+#pragma unroll 4
+  for (uint32_t i = 0; i < c.m; ++i) mask |= 1u << reduce(hash_top(keys[i], X), c.m);
+  uint64_t ok = __ballot(mask == c.fullmask);
+  return ok ? a0 + (uint64_t)__builtin_ctzll(ok) : kInf;
+}
+
+// Rotation fitting (Sec. 4): attempt t hashes with identifier t*m; keys of A
+// build a, keys of B build b; both must be collision free (popcount) and
+// some rotation of b must fill the holes of a.  Lanes passing the popcount
+// test are checked in lane order, each by the whole wave: lane r tests
+// rotation r, so the lowest valid r comes from one ballot.
+__device__ __forceinline__ uint64_t round_leaf_rot(const uint64_t* keys, const Node& c,
+                                                    uint64_t a0) {
+  const uint32_t lane = lane_id();
+  const uint64_t X = c.start + (a0 + lane) * c.m;
+  uint32_t a = 0, b = 0;
+#pragma unroll 4
+  for (uint32_t i = 0; i < c.na; ++i) a |= 1u << reduce(hash_top(keys[i], X), c.m);
+#pragma unroll 4
+  for (uint32_t i = c.na; i < c.m; ++i) b |= 1u << reduce(hash_top(keys[i], X), c.m);
+  bool cand = (uint32_t)__popc(a) == c.na && (uint32_t)__popc(b) == c.m - c.na;
+  uint64_t cm = __ballot(cand);
+  while (cm) {
+    const uint32_t L = (uint32_t)__builtin_ctzll(cm);
+    const uint32_t aL = __builtin_amdgcn_readlane(a, L);
+    const uint32_t bL = __builtin_amdgcn_readlane(b, L);
+    const uint32_t want = ~aL & c.fullmask;
+    const bool ok = lane < c.m && rot_m(bL, lane < c.m ? lane : 0, c.m, c.fullmask) == want;
+    const uint64_t okm = __ballot(ok);
+    if (okm) return (a0 + L) * c.m + (uint64_t)__builtin_ctzll(okm);
+    cm &= cm - 1;
+  }
+  return kInf;
+}
+
+// Exact check of one split seed by the whole wave: every key's child, then
+// per-child counts by ballot.
+__device__ bool verify_kway(const uint64_t* keys, const Node& c, uint64_t X) {
+  const uint32_t lane = lane_id();
+  uint32_t cnt = 0;  // lane j counts child j
+  for (uint32_t g = 0; g < c.m; g += 64) {
+    const uint32_t i = g + lane;
+    const bool v = i < c.m;
+    const uint32_t ch = v ? reduce(hash_top(keys[v ? i : 0], X), c.m) / c.unit : 0xFFFFFFFFu;
+    for (uint32_t j = 0; j < c.k; ++j) {
+      const uint32_t nj = (uint32_t)__popcll(__ballot(ch == j));
+      if (lane == j) cnt += nj;
+    }
+  }
+  const bool good = lane >= c.k || cnt == (lane + 1 < c.k ? c.unit : c.last);
+  return __ballot(!good) == 0;
+}
+
+// Lower/upper split: packed child counters, F bits per child, added with a
+// shift.  Fields can wrap, so a match of the packed word is only a
+// candidate; candidates get the exact check.
+template <bool kFull>
+__device__ __forceinline__ uint64_t round_split_kway(const uint64_t* keys, const Node& c,
+                                                      uint64_t a0) {
+  const uint64_t X = c.start + a0 + lane_id();
+  uint32_t acc = 0;
+  if (kFull) {
+#pragma unroll 4
+    for (uint32_t i = 0; i < c.m; ++i) {
+      const uint32_t ch = reduce(hash_top(keys[i], X), c.k);  // == floor(pos / unit) when m = k*unit
+      acc += 1u << __umul24(ch, c.F);
+    }
+  } else {
+#pragma unroll 4
+    for (uint32_t i = 0; i < c.m; ++i) {
+      const uint32_t p = reduce(hash_top(keys[i], X), c.m);
+      const uint32_t ch = __umul24(p, c.magic) >> 20;
+      acc += 1u << __umul24(ch, c.F);
+    }
+  }
+  uint64_t cm = __ballot(acc == c.target);
+  while (cm) {
+    const uint32_t L = (uint32_t)__builtin_ctzll(cm);
+    if (verify_kway(keys, c, c.start + a0 + L)) return a0 + L;
+    cm &= cm - 1;
+  }
+  return kInf;
+}
+
+// Fanout-2 split: one counter of keys going left; remap(h, m) < left is the
+// same as (top word of h) < ceil(left * 2^32 / m).
+__device__ __forceinline__ uint64_t round_split_binary(const uint64_t* keys, const Node& c,
+                                                        uint64_t a0) {
+  const uint64_t X = c.start + a0 + lane_id();
+  uint32_t cnt = 0;
+#pragma unroll 4
+  for (uint32_t i = 0; i < c.m; ++i) cnt += hash_top(keys[i], X) < c.thr ? 1u : 0u;
+  uint64_t ok = __ballot(cnt == c.unit);
+  return ok ? a0 + (uint64_t)__builtin_ctzll(ok) : kInf;
+}
+
+// One chunk: rounds of 256 attempts; a wave stops at its first valid
+// attempt or once its next attempt cannot beat the workgroup's best.
+template <typename RoundFn>
+__device__ __forceinline__ void run_chunk(const uint64_t* keys, const Node& c, uint64_t chunk,
+                                          uint32_t rounds, uint64_t* s_best, RoundFn fn) {
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint64_t base = chunk * (uint64_t)(rounds * kWG);
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint64_t a0 = base + (uint64_t)r * kWG + wave * 64u;
+    const uint64_t cur =
+        uni64(__hip_atomic_load(s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (a0 * c.mult >= cur) break;
+    const uint64_t v = fn(keys, c, a0);
+    if (v != kInf) {
+      if (lane_id() == 0)
+        __hip_atomic_fetch_min(s_best, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      break;
+    }
+  }
+}
+
+__device__ void eval_chunk(const uint64_t* keys, const Node& c, uint64_t chunk, uint32_t rounds,
+                           uint64_t* s_best) {
+  switch (c.kind) {
+    case kLeaf:
+      if (c.rotation) run_chunk(keys, c, chunk, rounds, s_best, round_leaf_rot);
+      else run_chunk(keys, c, chunk, rounds, s_best, round_leaf_brute);
+      break;
+    case kLower:
+    case kUpper:
+      if (c.full) run_chunk(keys, c, chunk, rounds, s_best, round_split_kway<true>);
+      else run_chunk(keys, c, chunk, rounds, s_best, round_split_kway<false>);
+      break;
+    default: run_chunk(keys, c, chunk, rounds, s_best, round_split_binary); break;
+  }
+}
+
+// Stage the task's keys in LDS.  Leaves put the keys of A (bit 0 of w0 clear)
+// first, in a stable order, and report |A|.
+__device__ void stage_keys(const Task& t, const JobDev& J, const Node& c, uint64_t* s_keys,
+                           uint32_t* s_na) {
+  const Key* src = J.keys[t.depth & 1] + t.key_off;
+  const uint32_t tid = threadIdx.x;
+  if (c.kind == kLeaf) {
+    if (tid < 64) {
+      const bool v = tid < c.m;
+      Key key = v ? src[tid] : Key{0, 0};
+      const bool isb = v && (key.w0 & 1u);
+      const uint64_t bm = __ballot(isb);
+      const uint64_t am = __ballot(v && !isb);
+      const uint32_t na = (uint32_t)__popcll(am);
+      const uint64_t below = mask_below(tid);
+      if (v) {
+        const uint32_t pos = isb ? na + (uint32_t)__popcll(bm & below) : (uint32_t)__popcll(am & below);
+        s_keys[pos] = key.w1;
+      }
+      if (tid == 0) *s_na = na;
+    }
+  } else {
+    for (uint32_t i = tid; i < c.m; i += kWG) s_keys[i] = src[i].w1;
+  }
+}
+
+// Redistribute a split node's keys into its children's ranges of the other
+// ping-pong array (stable within each child), then queue the children.  Run
+// by wave 0; thread 0 queues.
+__device__ void finalize_split(const SearchParams& P, const Task& t, const JobDev& J,
+                               const Node& c, uint64_t s) {
+  const uint32_t lane = lane_id();
+  const Key* src = J.keys[t.depth & 1] + t.key_off;
+  Key* dst = J.keys[(t.depth + 1) & 1] + t.key_off;
+  const uint64_t X = c.start + s;
+  uint32_t run = 0;  // lane j: keys already placed in child j
+  for (uint32_t g = 0; g < c.m; g += 64) {
+    const uint32_t i = g + lane;
+    const bool v = i < c.m;
+    const Key key = v ? src[i] : Key{0, 0};
+    const uint32_t p = reduce(hash_top(key.w1, X), c.m);
+    uint32_t ch = c.kind == kBinary ? (p >= c.unit ? 1u : 0u) : p / c.unit;
+    if (!v) ch = 0xFFFFFFFFu;
+    const uint32_t base = (uint32_t)__shfl((int)run, v ? (int)ch : 0);
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < c.k; ++j) {
+      const uint64_t mk = __ballot(ch == j);
+      if (ch == j) rank = (uint32_t)__popcll(mk & mask_below(lane));
+      if (lane == j) run += (uint32_t)__popcll(mk);
+    }
+    const uint32_t at = ch * c.unit + base + rank;
+    if (v && at < c.m) dst[at] = key;
+  }
+  const bool good = lane >= c.k || run == (lane + 1 < c.k ? c.unit : c.last);
+  const bool all_good = __ballot(!good) == 0;
+  __threadfence();
+  if (lane == 0) {
+    if (!all_good) set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
+    J.vals[t.node] = s;
+    J.msz[t.node] = c.m;
+    __hip_atomic_fetch_add(&P.ctl->evals_split, (s + 1) * c.m, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&P.ctl->splits, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t child_node = t.node + 1;
+    for (uint32_t j = 0; j < c.k; ++j) {
+      const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
+      if (sz >= 2 && t.depth + 1 >= kMaxDepth) {
+        set_error(P.ctl, (uint32_t)(-RS_ERR_UNSUPPORTED));
+      } else if (sz >= 2) {
+        const uint64_t slot = __hip_atomic_fetch_add(&P.ctl->tail, 1ull, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (slot >= P.ctl->total) {
+          set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
+        } else {
+          Task ct;
+          ct.key_off = t.key_off + (uint64_t)j * c.unit;
+          ct.node = child_node;
+          ct.m = sz;
+          ct.depth = (uint16_t)(t.depth + 1);
+          ct.job = t.job;
+          P.tasks[slot] = ct;
+          st_release(&P.ready[slot], 1u);
+        }
+      }
+      child_node += J.nodecnt[sz];
+    }
+    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ void finalize_leaf(const SearchParams& P, const Task& t, const JobDev& J,
+                              const Node& c, uint64_t v) {
+  if (threadIdx.x == 0) {
+    J.vals[t.node] = v;
+    J.msz[t.node] = c.m;
+    const uint64_t att = c.rotation ? v / c.m : v;
+    __hip_atomic_fetch_add(&P.ctl->evals_leaf, (att + 1) * c.m, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&P.ctl->leaves, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Drop one in-flight chunk of task st; returns true for the one caller that
+// must finalize (the task has a value and nothing is in flight any more).
+__device__ __forceinline__ bool release_chunk(TaskState* st) {
+  const uint64_t old =
+      __hip_atomic_fetch_add(&st->np, ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  if ((old & 0xFFFFFFFFull) != 1) return false;
+  if (ld_acquire(&st->best) == kInf) return false;
+  uint32_t expected = 0;
+  return __hip_atomic_compare_exchange_strong(&st->closed, &expected, 1u, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct Shared {
+  Task task;
+  uint64_t chunk;
+  uint64_t best;
+  uint64_t fin_value;
+  uint32_t action;
+  uint32_t na;
+  uint32_t fin;
+  uint32_t iter;
+  uint64_t arg;
+  int32_t pick;
+};
+
+// Work on task `slot` until this worker's claim is refused.  my_q (thread 0
+// only) is the queue slot this worker has reserved; a helper leaves as soon
+// as that slot is ready.
+__device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, uint64_t slot,
+                         bool own, uint64_t& my_q) {
+  const uint32_t tid = threadIdx.x;
+  Task t = sh.task;
+  t.key_off = uni64(t.key_off);
+  t.node = uni64(t.node);
+  t.m = uni(t.m);
+  t.depth = (uint16_t)uni(t.depth);
+  t.job = (uint16_t)uni(t.job);
+  const JobDev& J = P.jobs[t.job];
+  Node c = make_node(t, J, P.start, P.cap_shift);
+  stage_keys(t, J, c, s_keys, &sh.na);
+  __syncthreads();
+  if (c.kind == kLeaf) c.na = uni(sh.na);
+  const uint32_t rounds = c.kind == kLeaf ? P.rounds_leaf
+                        : c.kind == kBinary ? 1u
+                                            : P.rounds_split;
+  const uint64_t per_chunk = (uint64_t)rounds * kWG;
+  TaskState* st = P.states + slot;
+  for (;;) {
+    if (tid == 0) {
+      sh.fin = 0;
+      sh.best = kInf;
+      uint64_t chunk = kStop;
+      if (ld_relaxed(&P.ctl->error) != 0) {
+        chunk = kStop;
+      } else if (!own && my_q < kExhausted && ld_acquire(&P.ready[my_q]) != 0) {
+        chunk = kStop;
+      } else {
+        const uint64_t old = __hip_atomic_fetch_add(&st->np, (1ull << 32) | 1ull,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t ci = old >> 32;
+        const uint64_t best = ld_acquire(&st->best);
+        const uint64_t first = ci * per_chunk;
+        // every worker may hold one claimed chunk whose result is not in yet
+        if (first >= c.cap + (uint64_t)P.workers * per_chunk) {
+          if (best == kInf && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
+            record_failure(P.ctl, t, slot, st, ci);
+          sh.fin = release_chunk(st) ? 1u : 0u;
+        } else if (best != kInf && first * c.mult >= best) {
+          sh.fin = release_chunk(st) ? 1u : 0u;
+        } else {
+          chunk = ci;
+        }
+      }
+      sh.chunk = chunk;
+    }
+    __syncthreads();
+    const uint64_t chunk = sh.chunk;
+    if (chunk != kStop) {
+      eval_chunk(s_keys, c, chunk, rounds, &sh.best);
+      __syncthreads();
+      if (tid == 0) {
+        if (sh.best != kInf)
+          __hip_atomic_fetch_min(&st->best, sh.best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.fin = release_chunk(st) ? 1u : 0u;
+      }
+      __syncthreads();
+    }
+    if (sh.fin) {
+      if (tid == 0) sh.fin_value = ld_acquire(&st->best);
+      __syncthreads();
+      const uint64_t v = sh.fin_value;
+      if (c.kind == kLeaf) finalize_leaf(P, t, J, c, v);
+      else if (tid < 64) finalize_split(P, t, J, c, v);
+      __syncthreads();
+      return;
+    }
+    if (chunk == kStop) return;
+  }
+}
+
+}  // namespace
+
+extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams P) {
+  extern __shared__ uint64_t s_keys[];
+  __shared__ Shared sh;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t g = blockIdx.x;
+  uint64_t my_q = kNoSlot;  // thread 0 only
+  uint64_t last_finished = 0, idle_since = 0;
+  if (tid == 0) sh.iter = 0;
+  __syncthreads();
+  for (;;) {
+    __syncthreads();  // every thread has read the previous decision
+    if (tid == 0) {
+      uint32_t act = kActScan;
+      if (ld_relaxed(&P.ctl->error) != 0) {
+        act = kActExit;
+      } else {
+        if (my_q == kNoSlot) {
+          const uint64_t q = __hip_atomic_fetch_add(&P.ctl->head, 1ull, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+          my_q = q < P.ctl->total ? q : kExhausted;
+        }
+        if (my_q < kExhausted && ld_acquire(&P.ready[my_q]) != 0) {
+          act = kActOwn;
+          sh.arg = my_q;
+          my_q = kNoSlot;
+        } else if (my_q == kExhausted && ld_acquire(&P.ctl->finished) >= P.ctl->total) {
+          act = kActExit;
+        }
+      }
+      sh.action = act;
+      sh.pick = 0x7FFFFFFF;
+      sh.iter += 1;
+    }
+    __syncthreads();
+    uint32_t act = sh.action;
+    if (act == kActExit) break;
+    if (act == kActScan) {
+      const uint32_t W = P.workers;
+      const uint32_t rot = (g * 2654435761u + sh.iter * 40503u) % W;
+      for (uint32_t i = tid; i < W; i += kWG) {
+        uint32_t idx = i + rot;
+        if (idx >= W) idx -= W;
+        if (ld_relaxed(&P.active[idx]) >= 0) atomicMin(&sh.pick, (int32_t)i);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t next = kActRetry;
+        if (sh.pick != 0x7FFFFFFF) {
+          uint32_t idx = (uint32_t)sh.pick + rot;
+          if (idx >= W) idx -= W;
+          const int32_t a = ld_relaxed(&P.active[idx]);
+          if (a >= 0 && ld_acquire(&P.ready[a]) != 0) {
+            // join only searches that are long already: a task that ends in
+            // its first chunks gains nothing from more workers
+            const TaskState* ts = P.states + a;
+            if ((ld_relaxed(&ts->np) >> 32) >= kHelpAfter && ld_relaxed(&ts->best) == kInf) {
+              next = kActHelp;
+              sh.arg = (uint64_t)a;
+            }
+          }
+        }
+        if (next == kActRetry) {
+          // bug guard: no node finished for stall_ticks of the 100 MHz clock
+          const uint64_t fin = ld_relaxed(&P.ctl->finished);
+          const uint64_t now = __builtin_amdgcn_s_memrealtime();
+          if (fin != last_finished || idle_since == 0) {
+            last_finished = fin;
+            idle_since = now;
+          } else if (now - idle_since > P.stall_ticks) {
+            set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
+          }
+          __builtin_amdgcn_s_sleep(8);
+        } else {
+          idle_since = 0;
+        }
+        sh.action = next;
+      }
+      __syncthreads();
+      act = sh.action;
+      if (act == kActRetry) continue;
+    }
+    const uint64_t slot = sh.arg;
+    if (tid == 0) {
+      sh.task = P.tasks[slot];
+      if (act == kActOwn) st_relaxed(&P.active[g], (int32_t)slot);
+      idle_since = 0;
+    }
+    __syncthreads();
+    run_task(P, sh, s_keys, slot, act == kActOwn, my_q);
+    if (tid == 0 && act == kActOwn) st_relaxed(&P.active[g], (int32_t)-1);
+    __syncthreads();
+  }
+}
+
+}  // namespace rs
+
+namespace rs {
+
+hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, rs_search_kernel, kWG,
+                                                      lds_bytes);
+}
+
+hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(rs_search_kernel, dim3(grid), dim3(kWG), lds_bytes, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace rs

@@ -1,0 +1,182 @@
+"""ctypes binding of librecsplit.so (include/recsplit.h).
+
+Argument marshalling only: every step of construction and evaluation runs
+in the library's HIP kernels.  Keys are (n, 2) arrays of (w0, w1) words:
+numpy uint64 arrays live in host memory; torch tensors on a HIP device
+(int64 or uint64, contiguous) are passed by device pointer.  Importing this
+module imports torch first (one HIP runtime per process), then loads the
+library, and raises if it has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+# torch first: its HIP runtime is then the one this library binds to (by
+# soname), so a process never holds two HIP runtimes and device pointers from
+# torch tensors and from the library live in the same context.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librecsplit.so")
+
+RS_FLAG_ROTATION = 1
+RS_FLAG_KEYS_ON_DEVICE = 2
+RS_FLAG_KEEP_VALUES = 4
+
+ERRORS = {0: "RS_OK", -1: "RS_ERR_INVALID_ARG", -2: "RS_ERR_DUPLICATE", -3: "RS_ERR_OOM",
+          -4: "RS_ERR_DEVICE", -5: "RS_ERR_CORRUPT", -6: "RS_ERR_SEARCH_LIMIT",
+          -7: "RS_ERR_UNSUPPORTED"}
+
+
+class RecSplitError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({_lib.rs_strerror(code).decode()})")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("nb", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
+                ("split_nodes", ctypes.c_uint64), ("leaf_nodes", ctypes.c_uint64),
+                ("useful_evals_split", ctypes.c_uint64), ("useful_evals_leaf", ctypes.c_uint64),
+                ("gr_bits", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("max_bucket", ctypes.c_uint32), ("workers", ctypes.c_uint32),
+                ("ms_sort", ctypes.c_double), ("ms_search", ctypes.c_double),
+                ("ms_encode", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ValuRates(ctypes.Structure):
+    _fields_ = [("add_u32", ctypes.c_double), ("xor_b32", ctypes.c_double),
+                ("mul_lo_u32", ctypes.c_double), ("mul_hi_u32", ctypes.c_double),
+                ("mad_u64_u32", ctypes.c_double), ("lshrrev_b64", ctypes.c_double),
+                ("lshl_add_u64", ctypes.c_double), ("add3_u32", ctypes.c_double),
+                ("hash_evals", ctypes.c_double), ("compute_units", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_lib.rs_build.argtypes = [_vp, _u64, _u32, _u32, _u32, ctypes.POINTER(_vp)]
+_lib.rs_query.argtypes = [_vp, _vp, _u64, _vp, _u32]
+_lib.rs_serialize.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64)]
+_lib.rs_deserialize.argtypes = [_vp, _u64, ctypes.POINTER(_vp)]
+_lib.rs_debug_node_values.argtypes = [_vp, _u64, _vp, _u64, ctypes.POINTER(_u64)]
+_lib.rs_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+_lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
+_lib.rs_free.argtypes = [_vp]
+_lib.rs_free.restype = None
+_lib.rs_strerror.argtypes = [ctypes.c_int]
+_lib.rs_strerror.restype = ctypes.c_char_p
+for _f in ("rs_build", "rs_query", "rs_serialize", "rs_deserialize", "rs_debug_node_values",
+           "rs_get_stats", "rs_calibrate_valu"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+def library():
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise RecSplitError(rc, where)
+
+
+def _keys_arg(keys):
+    """(pointer, n, flags, keepalive) for host numpy or device torch keys."""
+    if isinstance(keys, np.ndarray):
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        if k.ndim != 2 or k.shape[1] != 2:
+            raise ValueError("keys must have shape (n, 2)")
+        return k.ctypes.data if k.size else None, k.shape[0], 0, k
+    if not isinstance(keys, torch.Tensor) or keys.device.type != "cuda":
+        raise TypeError("keys must be a numpy array or a torch tensor on a HIP device")
+    if keys.dim() != 2 or keys.shape[1] != 2 or keys.element_size() != 8 or not keys.is_contiguous():
+        raise ValueError("device keys must be a contiguous (n, 2) tensor of 64-bit words")
+    return keys.data_ptr() if keys.numel() else None, keys.shape[0], RS_FLAG_KEYS_ON_DEVICE, keys
+
+
+class MPHF:
+    """A built (or deserialised) minimal perfect hash function."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.rs_free(h)
+            self._h = ctypes.c_void_p(0)
+
+    def serialize(self) -> bytes:
+        p, n = ctypes.c_void_p(), ctypes.c_uint64()
+        _check(_lib.rs_serialize(self._h, ctypes.byref(p), ctypes.byref(n)), "rs_serialize")
+        return ctypes.string_at(p.value, n.value)
+
+    def query(self, keys, out=None):
+        ptr, n, flags, keep = _keys_arg(keys)
+        if flags & RS_FLAG_KEYS_ON_DEVICE:
+            if out is None:
+                out = torch.empty(n, dtype=torch.int64, device=keys.device)
+            _check(_lib.rs_query(self._h, ptr, n, out.data_ptr() if n else None, flags), "rs_query")
+            return out
+        res = np.zeros(n, dtype=np.uint64)
+        _check(_lib.rs_query(self._h, ptr, n, res.ctypes.data if n else None, 0), "rs_query")
+        return res
+
+    def node_values(self, bucket: int) -> np.ndarray:
+        cnt = ctypes.c_uint64()
+        _lib.rs_debug_node_values(self._h, bucket, None, 0, ctypes.byref(cnt))
+        out = np.zeros(max(cnt.value, 1), dtype=np.uint64)
+        _check(_lib.rs_debug_node_values(self._h, bucket, out.ctypes.data, len(out),
+                                         ctypes.byref(cnt)), "rs_debug_node_values")
+        return out[:cnt.value]
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(_lib.rs_get_stats(self._h, ctypes.byref(st)), "rs_get_stats")
+        return st.as_dict()
+
+
+def build(keys, leaf_size: int, bucket_size: int, rotation: bool = True,
+          keep_values: bool = False) -> MPHF:
+    """rs_build on host (numpy) or device (torch) keys."""
+    ptr, n, flags, keep = _keys_arg(keys)
+    flags |= (RS_FLAG_ROTATION if rotation else 0) | (RS_FLAG_KEEP_VALUES if keep_values else 0)
+    h = ctypes.c_void_p()
+    _check(_lib.rs_build(ptr, n, leaf_size, bucket_size, flags, ctypes.byref(h)), "rs_build")
+    return MPHF(h.value)
+
+
+def deserialize(data: bytes) -> MPHF:
+    buf = np.frombuffer(data, dtype=np.uint8)
+    h = ctypes.c_void_p()
+    _check(_lib.rs_deserialize(buf.ctypes.data if len(buf) else None, len(buf), ctypes.byref(h)),
+           "rs_deserialize")
+    return MPHF(h.value)
+
+
+def strerror(code: int) -> str:
+    return _lib.rs_strerror(code).decode()
+
+
+def calibrate_valu() -> dict:
+    """Issue rates of the VALU instruction classes of a hash evaluation."""
+    r = ValuRates()
+    _check(_lib.rs_calibrate_valu(ctypes.byref(r)), "rs_calibrate_valu")
+    return r.as_dict()

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Bit-exact is the bar everywhere (construction is integer work): the same
+serialised bytes, the same node values, the same query results -- also for
+keys outside the set, since both sides evaluate the same function.  Small
+cases cover several buckets, ragged last leaves, singleton children, empty
+and one-key sets, l from 2 to 16 and b from 1 to 4096; the benchmark
+configurations follow at full size (the l = 16, b = 2000 build on a sample
+of buckets the oracle can afford).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_09562_amd import keygen
+
+pytestmark = pytest.mark.gpu
+
+
+def rs():
+    from paper_2212_09562_amd import recsplit
+
+    return recsplit
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _first_diff_bucket(f, data, nb):
+    for j in range(nb):
+        a = f.node_values(j)
+        b = oracle.bucket_values(data, j)
+        if not np.array_equal(a, b):
+            return j, a, b
+    return None
+
+
+def _check_parity(keys, l, b, rot, tag=""):
+    _case(f"n={len(keys)} l={l} b={b} rot={rot} {tag}")
+    want, st = oracle.build(keys, l, b, rot)
+    f = rs().build(keys, l, b, rot, keep_values=True)
+    got = f.serialize()
+    if got != want:
+        nb = oracle.num_buckets(len(keys), b)
+        d = _first_diff_bucket(f, want, nb)
+        raise AssertionError(f"bytes differ ({len(got)} vs {len(want)}); first bucket with other "
+                             f"values: {d}")
+    gs = f.stats()
+    assert gs["useful_evals_split"] == st["evals_split"]
+    assert gs["useful_evals_leaf"] == st["evals_leaf"]
+    assert gs["split_nodes"] == st["nodes_split"] and gs["leaf_nodes"] == st["nodes_leaf"]
+    r = f.query(keys)
+    assert np.array_equal(np.sort(r), np.arange(len(keys), dtype=np.uint64))
+    assert np.array_equal(r, oracle.query(want, keys))
+    return f, want
+
+
+SMALL = [
+    (0, 8, 100, True), (1, 8, 100, True), (2, 8, 2, False), (3, 2, 1, True), (17, 5, 7, False),
+    (1000, 8, 100, False), (1000, 8, 100, True), (3000, 2, 7, True), (3000, 3, 50, False),
+    (4000, 4, 30, True), (5000, 5, 100, True), (5000, 7, 300, False), (6000, 10, 500, True),
+    (8000, 12, 1000, True), (3000, 12, 60, False), (20000, 8, 100, True), (20000, 6, 1, True),
+]
+
+
+@pytest.mark.parametrize("n,l,b,rot", SMALL)
+def test_small_parity(n, l, b, rot):
+    _check_parity(keygen.fingerprints(n, 100 + n + l), l, b, rot)
+
+
+def test_non_members_match_oracle():
+    keys = keygen.fingerprints(30000, 9)
+    _case("non-member queries, n=30000 l=8 b=100")
+    f, data = _check_parity(keys, 8, 100, True)
+    other = keygen.fingerprints(20000, 10)
+    assert np.array_equal(f.query(other), oracle.query(data, other))
+
+
+def test_device_keys_and_determinism():
+    import torch
+
+    keys = keygen.fingerprints(50000, 12)
+    _case("device keys, repeat, other launch shapes: n=50000 l=8 b=100")
+    want, _ = oracle.build(keys, 8, 100, True)
+    dk = torch.from_numpy(keys.view(np.int64)).cuda()
+    f = rs().build(dk, 8, 100, True)
+    assert f.serialize() == want
+    r = f.query(dk)
+    torch.cuda.synchronize()
+    assert np.array_equal(r.cpu().numpy().view(np.uint64), oracle.query(want, keys))
+    # a shuffled copy and a different chunk schedule give the same bytes
+    perm = np.random.default_rng(0).permutation(len(keys))
+    old = {k: os.environ.get(k) for k in ("RS_ROUNDS_LEAF", "RS_ROUNDS_SPLIT")}
+    try:
+        os.environ["RS_ROUNDS_LEAF"] = "1"
+        os.environ["RS_ROUNDS_SPLIT"] = "3"
+        assert rs().build(keys[perm], 8, 100, True).serialize() == want
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    assert rs().build(keys, 8, 100, True).serialize() == want
+
+
+def test_serialise_roundtrip_and_corruption():
+    keys = keygen.fingerprints(10000, 13)
+    _case("deserialise, n=10000 l=8 b=100")
+    f = rs().build(keys, 8, 100, True)
+    data = f.serialize()
+    g = rs().deserialize(data)
+    assert g.serialize() == data
+    assert np.array_equal(g.query(keys), f.query(keys))
+    bad = bytearray(data)
+    bad[0] ^= 1
+    with pytest.raises(rs().RecSplitError) as e:
+        rs().deserialize(bytes(bad))
+    assert e.value.code == -5
+    with pytest.raises(rs().RecSplitError) as e:
+        rs().deserialize(data[:-8])
+    assert e.value.code == -5
+
+
+def test_duplicates_and_bad_arguments():
+    keys = keygen.fingerprints(2000, 14)
+    _case("duplicate w1 in one bucket")
+    dup = keys.copy()
+    dup[5, 1] = dup[6, 1]
+    dup[5, 0] = dup[6, 0] ^ np.uint64(1)
+    with pytest.raises(rs().RecSplitError) as e:
+        rs().build(dup, 8, 100, True)
+    assert e.value.code == -2
+    for l, b in ((1, 100), (25, 100), (8, 0), (8, 4097)):
+        with pytest.raises(rs().RecSplitError) as e:
+            rs().build(keys, l, b, True)
+        assert e.value.code == -1
+    # the library is still usable after the errors
+    _check_parity(keys, 8, 100, True, "after errors")
+
+
+def test_largest_buckets():
+    _case("b=4096, n=12000, l=8")
+    _check_parity(keygen.fingerprints(12000, 15), 8, 4096, True)
+
+
+def test_leaf16_two_buckets():
+    _case("l=16 b=2000 n=4000 (two buckets)")
+    _check_parity(keygen.fingerprints(4000, 16), 16, 2000, True)
+
+
+@pytest.mark.parametrize("rot,seed,n", [(False, 1, 100000), (True, 2, 1000000)])
+def test_configs_l8_b100_full(rot, seed, n):
+    """Plain RecSplit on 10^5 keys and rotation fitting on 10^6 keys, l=8, b=100."""
+    keys = keygen.fingerprints(n, seed)
+    _check_parity(keys, 8, 100, rot, "full configuration")
+
+
+def _record_bits(words, gr_off, start, nbits):
+    out = np.zeros((nbits + 63) // 64, dtype=np.uint64)
+    for i in range(len(out)):
+        lo = start + 64 * i
+        w, s = lo // 64, lo % 64
+        v = int(words[gr_off + w]) >> s
+        if s and gr_off + w + 1 < len(words):
+            v |= int(words[gr_off + w + 1]) << (64 - s)
+        take = min(64, nbits - 64 * i)
+        out[i] = v & ((1 << take) - 1)
+    return out
+
+
+def _parse_offsets(data):
+    """Bucket prefix sums C and record offsets P decoded from the bytes."""
+    w = np.frombuffer(data, dtype=np.uint64)
+    at = 5
+    seqs = []
+    for _ in range(2):
+        N, U, L, lw, ub, uw = (int(x) for x in w[at:at + 6])
+        lower = w[at + 6:at + 6 + lw]
+        upper = w[at + 6 + lw:at + 6 + lw + uw]
+        bits = np.unpackbits(upper.view(np.uint8), bitorder="little")[:ub]
+        ones = np.flatnonzero(bits)
+        hi = ones - np.arange(N)
+        lows = np.unpackbits(lower.view(np.uint8), bitorder="little")[:N * L].reshape(N, L) \
+            if L else np.zeros((N, 0), dtype=np.uint8)
+        lo = (lows.astype(np.uint64) << np.arange(L, dtype=np.uint64)).sum(axis=1) if L else 0
+        seqs.append((hi.astype(np.uint64) << np.uint64(L)) | lo)
+        at += 6 + lw + uw
+    return seqs[0], seqs[1], at + 2, w
+
+
+def test_config_l16_b2000_sampled():
+    """10^7 keys, l=16, b=2000, rotation fitting: the whole build on the GPU,
+    checked on a sample of buckets rebuilt by the oracle (values and their
+    Golomb-Rice records), on the bucket sizes, and on the ranks of all keys."""
+    import torch
+
+    n, l, b = 10_000_000, 16, 2000
+    keys = keygen.fingerprints(n, 3)
+    _case("n=1e7 l=16 b=2000 rot, sampled buckets")
+    dk = torch.from_numpy(keys.view(np.int64)).cuda()
+    f = rs().build(dk, l, b, True, keep_values=True)
+    data = f.serialize()
+    nb = oracle.num_buckets(n, b)
+    C, P, gr_off, words = _parse_offsets(data)
+    bucket = ((keys[:, 0].astype(object) * nb) >> 64).astype(np.int64)
+    assert np.array_equal(np.diff(C.astype(np.int64)), np.bincount(bucket, minlength=nb))
+    sel = [0, 2500, nb - 1]
+    recs, st = oracle.build_buckets(keys, l, b, True, sel)
+    for (j, size, vals, rec_words, rec_bits) in recs:
+        assert np.array_equal(f.node_values(j), vals), j
+        assert int(P[j + 1] - P[j]) == rec_bits
+        assert np.array_equal(_record_bits(words, gr_off, int(P[j]), rec_bits), rec_words), j
+    r = f.query(dk)
+    rs_sorted = torch.sort(r)[0]
+    assert torch.equal(rs_sorted, torch.arange(n, device=r.device, dtype=r.dtype))
+    # ranks of a sample of keys against the oracle's evaluation of the same bytes
+    idx = np.random.default_rng(1).choice(n, 2000, replace=False)
+    assert np.array_equal(r[torch.from_numpy(idx).cuda()].cpu().numpy().view(np.uint64),
+                          oracle.query(data, keys[idx]))
+    bits = len(data) * 8 / n
+    assert math.log2(math.e) <= bits < 1.56 + 0.06

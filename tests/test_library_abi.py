@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI library (no GPU needed, no compute calls)."""
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "recsplit.h")).read()
+    return sorted(set(re.findall(r"\b(rs_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("rs_build", "rs_query", "rs_serialize", "rs_deserialize", "rs_free",
+                 "rs_strerror", "rs_get_stats", "rs_debug_node_values", "rs_calibrate_valu"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2212_09562_amd import recsplit
+
+    lib = recsplit.library()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_error_strings():
+    from paper_2212_09562_amd import recsplit
+
+    for code in range(0, -8, -1):
+        s = recsplit.strerror(code)
+        assert s and s != "unknown error"
+    assert recsplit.strerror(-99) == "unknown error"
+
+
+def test_invalid_arguments_rejected_before_any_device_call():
+    import numpy as np
+
+    from paper_2212_09562_amd import recsplit
+
+    keys = np.zeros((4, 2), dtype=np.uint64)
+    for l, b in ((1, 100), (25, 100), (8, 0), (8, 4097)):
+        with pytest.raises(recsplit.RecSplitError) as e:
+            recsplit.build(keys, l, b)
+        assert e.value.code == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_keygen_is_duplicate_free_and_deterministic():
+    import numpy as np
+
+    from paper_2212_09562_amd import keygen
+
+    a = keygen.fingerprints(100000, 7)
+    b = keygen.fingerprints(100000, 7)
+    assert np.array_equal(a, b)
+    assert len(np.unique(a.view(np.dtype((np.void, 16))))) == len(a)
+    jobs = keygen.batched_jobs(8, seed=4)
+    assert all(1000 <= j["n"] <= 1_000_000 and j["leaf_size"] in (8, 12, 16)
+               and j["bucket_size"] in (100, 500, 2000) for j in jobs)
+    reqs = keygen.served_requests(50)
+    assert all(reqs[i]["arrival"] < reqs[i + 1]["arrival"] for i in range(49))
