@@ -8,16 +8,18 @@ fingerprints that are resident in HBM before the timed region starts.
 
 Prints one JSON line.  `roofline` prices the seed-search kernel (the
 dominant one) on the integer-VALU roofline: achieved = useful hash
-evaluations x full-rate issue slots per evaluation / search-kernel time,
-with the slot cost of each instruction class measured live by the library's
-calibration kernels; peak = 256 CU x 64 lanes x 2.4 GHz.  `cpu_baseline` is
-the CPU oracle timed on a bounded sample of the same key set.
+evaluations (those the sequential definition performs, a function of the
+chosen seeds) x 19 VALU instructions per evaluation / search-kernel time
+(HIP events on the kernel's stream); peak = 256 CU x 64 lanes x 2.4 GHz.
+Beside it: the library's live calibration of the same instruction sequence
+with the keys in registers and no memory traffic.  `cpu_baseline` is the
+CPU oracle timed on a bounded sample of the same key set.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -28,27 +30,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MPHF construction keys/sec at ℓ=16,b=2000 (bit-exact) + % int-ALU roofline"
-PEAK_LANE_OPS = 256 * 64 * 2.4e9  # full-rate 32-bit VALU lane operations per second
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: full-rate 32-bit VALU lane-operations per second
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# One hash evaluation plus its position/count update, as issued by the
-# search kernel's inner loop (per key, per lane).
-INSTRUCTION_MIX = {
-    "lshl_add_u64": 1,  # w1 + seed identifier (64-bit)
-    "lshrrev_b64": 2,   # z >> 30, z >> 27
-    "xor_b32": 5,       # the two 64-bit xorshifts, final xorshift of the top word
-    "mad_u64_u32": 1,   # first multiply: low x low (64-bit result)
-    "mul_lo_u32": 4,    # cross terms of both multiplies
-    "mul_hi_u32": 2,    # top word of the second multiply; reduction to a position
-    "add3_u32": 2,      # high-word sums of both multiplies
-    "add_u32": 2,       # shift of the top word; bit / counter update
-}
+# One hash evaluation plus its position/count update, as issued per key and
+# lane by the search kernel's inner loop (counted from the gfx950 ISA):
+# 64-bit add of the identifier, two 64-bit xorshifts (shift + 2 xor each),
+# two 64x64 multiplies (3 multiply-class + 1 add3 each; the second keeps only
+# the high word), the final xorshift of the top word (2), the multiply-high
+# reduction to a position or child (1) and the bit/counter update (1).
+OPS_PER_EVAL = 19
+INSTRUCTION_MIX = {"lshl_add_u64": 1, "lshrrev_b64": 2, "xor_b32": 5, "mad_u64_u32": 1,
+                   "mul_lo_u32": 4, "mul_hi_u32": 2, "add3_u32": 2, "add_u32": 2}
+assert sum(INSTRUCTION_MIX.values()) == OPS_PER_EVAL
 
 WORKLOAD = {"n": 10_000_000, "leaf_size": 16, "bucket_size": 2000, "rotation": True, "seed": 3}
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "rs_search_kernel.l16_b2000_n1e7.pmc.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2212_09562_amd", "csrc", f)
+                  for f in ("rs_search.hip", "rs_internal.h")]
 
 
-def slots_per_eval(rates: dict) -> float:
-    ref = rates["add_u32"]
-    return sum(n * ref / rates[k] for k, n in INSTRUCTION_MIX.items())
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per search launch from the committed PMC summary, if it was
+    taken on the current kernel source; else None."""
+    try:
+        fields = dict(line.split(":", 1) for line in open(PMC_SUMMARY) if ":" in line)
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(keys, l, b, buckets):
@@ -71,8 +93,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=WORKLOAD["n"])
-    ap.add_argument("--cpu-buckets", type=int, default=2)
+    ap.add_argument("--cpu-buckets", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-check", action="store_true",
+                    help="run a plain 256 MiB device copy first (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the construction is not "
@@ -88,8 +112,14 @@ def main():
     keys = keygen.fingerprints(n, WORKLOAD["seed"])
     dev = torch.from_numpy(keys.view(np.int64)).cuda()
     torch.cuda.synchronize()
+    if args.copy_check:
+        src = torch.ones(1 << 25, dtype=torch.int64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     rates = recsplit.calibrate_valu()
-    w_alg = slots_per_eval(rates)
 
     for _ in range(args.warmup):
         recsplit.build(dev, l, b, rot).free()
@@ -107,8 +137,9 @@ def main():
     evals = st["useful_evals_split"] + st["useful_evals_leaf"]
     ms_search = sum(s["ms_search"] for s in stats) / len(stats)
     evals_per_s = evals / (ms_search * 1e-3)
-    achieved = evals_per_s * w_alg / 1e12
+    achieved = evals_per_s * OPS_PER_EVAL / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    traffic = measured_traffic()
     out = {
         "metric": METRIC,
         "value": n * args.steps / secs,
@@ -126,11 +157,12 @@ def main():
                    "n": n, "leaf_size": l, "bucket_size": b, "rotation": rot,
                    "global_batch": n, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": "rs_search_kernel", "ms_per_launch": ms_search,
-                     "useful_hash_evals": evals, "slots_per_eval": w_alg,
+                     "useful_hash_evals": evals, "ops_per_eval": OPS_PER_EVAL,
                      "hash_evals_per_s": evals_per_s,
-                     "calibrated_hash_loop_evals_per_s": rates["hash_evals"]},
+                     "calibrated_hash_loop_evals_per_s": rates["hash_evals"],
+                     "frac_of_calibrated_hash_loop": evals_per_s / rates["hash_evals"]},
         "bits_per_key": st["bytes"] * 8 / n,
         "stage_ms": {k: sum(s[k] for s in stats) / len(stats)
                      for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},
