@@ -162,7 +162,9 @@ def main():
                      "useful_hash_evals": evals, "ops_per_eval": OPS_PER_EVAL,
                      "hash_evals_per_s": evals_per_s,
                      "calibrated_hash_loop_evals_per_s": rates["hash_evals"],
-                     "frac_of_calibrated_hash_loop": evals_per_s / rates["hash_evals"]},
+                     "frac_of_calibrated_hash_loop": evals_per_s / rates["hash_evals"],
+                     "sustained_hash_loop_evals_per_s": rates["hash_evals_sustained"],
+                     "frac_of_sustained_hash_loop": evals_per_s / rates["hash_evals_sustained"]},
         "bits_per_key": st["bytes"] * 8 / n,
         "stage_ms": {k: sum(s[k] for s in stats) / len(stats)
                      for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},

@@ -80,6 +80,24 @@ int rs_build(const rs_key128 *keys, uint64_t n, uint32_t leaf_size, uint32_t buc
              uint32_t flags, rs_mphf **out);
 
 /*
+ * Build many independent key sets at once.  Each job is what rs_build takes;
+ * the buckets of all jobs are sorted job by job, then every node of every job
+ * is searched by one persistent launch (one device work queue), then every
+ * job is encoded.  outs[i] receives job i's structure (NULL on failure) and
+ * statuses[i] its result code; a job that fails (a duplicate, an argument out
+ * of range) does not affect the others, and every result is identical to
+ * what rs_build makes of that job alone.  Returns RS_OK or the first non-zero
+ * status.  jobs, outs and statuses have njobs entries (njobs < 65536).
+ */
+typedef struct {
+  const rs_key128 *keys;
+  uint64_t n;
+  uint32_t leaf_size, bucket_size, flags;
+} rs_job;
+
+int rs_build_batch(const rs_job *jobs, uint32_t njobs, rs_mphf **outs, int *statuses);
+
+/*
  * Evaluate the function on n keys (Sec. 2.2 "Query": bucket, tree descent,
  * leaf position; Sec. 4: keys of B add the rotation modulo the leaf size).
  * Runs in a HIP kernel.  keys/out are host pointers, or device pointers with
@@ -124,12 +142,13 @@ int rs_get_stats(const rs_mphf *f, rs_stats *st);
  * in lane-operations per second on the current device, each measured over
  * independent dependency chains at full occupancy; and the rate of the hash
  * trial sequence itself (16 keys in registers, no memory), in hash
- * evaluations per second.  Runs a few short kernels; no other side effects.
+ * evaluations per second, over a few milliseconds and over about two seconds
+ * (the clock held under sustained load).  No other side effects.
  */
 typedef struct {
   double add_u32, xor_b32, mul_lo_u32, mul_hi_u32, mad_u64_u32, lshrrev_b64, lshl_add_u64,
       add3_u32;
-  double hash_evals;
+  double hash_evals, hash_evals_sustained;
   uint32_t compute_units;
 } rs_valu_rates;
 

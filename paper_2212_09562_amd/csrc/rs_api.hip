@@ -116,7 +116,7 @@ struct Device {
   uint64_t* start = nullptr;  // starting seed of depth d: SplitMix64(0) output d+1
   Tables tables[kMaxLeaf + 1];
   Buffer keys_in, k0, k1, cnt, fill, off, tmp, nodes, node_base, vals, msz, tasks, states, ready_f,
-      active, ctl, jobs, len, pos, qkeys, qout, sc_counts, sc_prefix;
+      active, ctl, jobs, jinfo, len, pos, qkeys, qout, sc_counts, sc_prefix;
   hipEvent_t ev[6];
 };
 
@@ -256,68 +256,129 @@ int attach_device(Device& d, rs_mphf* f, bool words_on_device) {
   return RS_OK;
 }
 
-int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b,
-                 uint32_t flags, rs_mphf** out) {
-  const hipStream_t s = 0;
-  const uint64_t nb = n ? (n + b - 1) / b : 1;
-  const bool rotation = (flags & RS_FLAG_ROTATION) != 0;
+// One job of a build: its inputs, its slices of the shared device arrays, and
+// its outcome.
+struct JobPlan {
+  const Key* keys = nullptr;  // caller's keys (host or device, per flags)
+  uint64_t n = 0;
+  uint32_t l = 0, b = 0, flags = 0;
+  uint64_t nb = 0;
+  uint64_t key_base = 0;     // first key in the work arrays
+  uint64_t bucket_base = 0;  // first bucket in per-bucket arrays of nb entries
+  uint64_t off_base = 0;     // first entry in per-bucket arrays of nb + 1 entries
+  uint64_t host_base = 0;    // first key in the staging copy of host keys
+  uint64_t node_off = 0, total = 0;
+  uint32_t maxm = 0;
+  int status = RS_OK;
   Tables* T = nullptr;
-  int rc = tables_for(d, l, &T);
-  if (rc) return rc;
+  rs_mphf* out = nullptr;
+};
 
-  HIPCHECK(hipEventRecord(d.ev[0], s));
-  const Key* kin = reinterpret_cast<const Key*>(keys);
-  if (!(flags & RS_FLAG_KEYS_ON_DEVICE) && n) {
-    HIPCHECK(ensure(d.keys_in, n * sizeof(Key)));
-    HIPCHECK(hipMemcpy(d.keys_in.p, keys, n * sizeof(Key), hipMemcpyHostToDevice));
-    kin = as<Key>(d.keys_in);
+int encode_job(Device& d, JobPlan& jp, const JobInfo& info, double ms_sort, double ms_search,
+               uint32_t workers, hipStream_t s);
+
+// Build every job whose status is RS_OK on entry; on return each job has its
+// status and, on success, its structure.  One search launch serves all jobs.
+int build_jobs(Device& d, std::vector<JobPlan>& jobs) {
+  const hipStream_t s = 0;
+  const uint32_t nj = (uint32_t)jobs.size();
+  uint64_t nkeys = 0, nbk = 0, noff = 0, nhost = 0;
+  for (JobPlan& j : jobs) {
+    j.nb = j.n ? (j.n + j.b - 1) / j.b : 1;
+    j.key_base = nkeys;
+    j.bucket_base = nbk;
+    j.off_base = noff;
+    j.host_base = nhost;
+    nkeys += j.n;
+    nbk += j.nb;
+    noff += j.nb + 1;
+    if (!(j.flags & RS_FLAG_KEYS_ON_DEVICE)) nhost += j.n;
+    int rc = tables_for(d, j.l, &j.T);
+    if (rc) return rc;
   }
-  HIPCHECK(ensure(d.k0, n * sizeof(Key)));
-  HIPCHECK(ensure(d.k1, n * sizeof(Key)));
-  HIPCHECK(ensure(d.cnt, nb * sizeof(uint32_t)));
-  HIPCHECK(ensure(d.fill, nb * sizeof(uint32_t)));
-  HIPCHECK(ensure(d.off, (nb + 1) * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.nodes, nb * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.node_base, (nb + 1) * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.len, nb * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.pos, (nb + 1) * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.tmp, scan_tmp_words(nb + 1) * sizeof(uint64_t)));
+  uint64_t max_nb = 1;
+  for (JobPlan& j : jobs) max_nb = j.nb > max_nb ? j.nb : max_nb;
+  HIPCHECK(hipEventRecord(d.ev[0], s));
+  if (nhost) HIPCHECK(ensure(d.keys_in, nhost * sizeof(Key)));
+  HIPCHECK(ensure(d.k0, nkeys * sizeof(Key)));
+  HIPCHECK(ensure(d.k1, nkeys * sizeof(Key)));
+  HIPCHECK(ensure(d.cnt, nbk * sizeof(uint32_t)));
+  HIPCHECK(ensure(d.fill, nbk * sizeof(uint32_t)));
+  HIPCHECK(ensure(d.nodes, nbk * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.len, nbk * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.off, noff * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.node_base, noff * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.pos, noff * sizeof(uint64_t)));
+  HIPCHECK(ensure(d.tmp, scan_tmp_words(max_nb + 1) * sizeof(uint64_t)));
   HIPCHECK(ensure(d.ctl, sizeof(Control)));
+  HIPCHECK(ensure(d.jinfo, nj * sizeof(JobInfo)));
+  HIPCHECK(ensure(d.jobs, nj * sizeof(JobDev)));
   Control* ctl = as<Control>(d.ctl);
+  JobInfo* jinfo = as<JobInfo>(d.jinfo);
+  for (JobPlan& j : jobs)
+    if (!(j.flags & RS_FLAG_KEYS_ON_DEVICE) && j.n)
+      HIPCHECK(hipMemcpy(as<Key>(d.keys_in) + j.host_base, j.keys, j.n * sizeof(Key),
+                         hipMemcpyHostToDevice));
   HIPCHECK(hipEventRecord(d.ev[1], s));
 
-  // 1. buckets: sizes, borders, scatter, duplicate check
+  // 1. buckets: sizes, borders, scatter, duplicate check, node counts
   HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(ctl), sizeof(Control) / 8, 0, s));
-  HIPCHECK(fill_u32(as<uint32_t>(d.cnt), nb, 0, s));
-  HIPCHECK(fill_u32(as<uint32_t>(d.fill), nb, 0, s));
-  HIPCHECK(bucket_histogram(kin, n, nb, as<uint32_t>(d.cnt), ctl, s));
-  HIPCHECK(scan_excl_u32(as<uint32_t>(d.cnt), nb, as<uint64_t>(d.off), as<uint64_t>(d.tmp), s));
-  HIPCHECK(bucket_scatter(kin, n, nb, as<uint64_t>(d.off), as<uint32_t>(d.fill), as<Key>(d.k0), s));
-  Control h_ctl;
-  HIPCHECK(hipMemcpy(&h_ctl, ctl, sizeof h_ctl, hipMemcpyDeviceToHost));
-  if (h_ctl.maxm > kMaxBucketKeys) return RS_ERR_UNSUPPORTED;
-  const uint32_t maxm = h_ctl.maxm;
-  {
-    uint32_t p2 = 1;
-    while (p2 < maxm) p2 <<= 1;
-    // LDS of the duplicate check (next power of two) and of the search stage
-    if ((uint64_t)p2 * 8 + 1024 > (uint64_t)d.lds_per_block) return RS_ERR_UNSUPPORTED;
+  HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(jinfo), nj * sizeof(JobInfo) / 8, 0, s));
+  HIPCHECK(fill_u32(as<uint32_t>(d.cnt), nbk, 0, s));
+  HIPCHECK(fill_u32(as<uint32_t>(d.fill), nbk, 0, s));
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    const Key* kin =
+        (j.flags & RS_FLAG_KEYS_ON_DEVICE) ? j.keys : as<Key>(d.keys_in) + j.host_base;
+    uint32_t* cnt = as<uint32_t>(d.cnt) + j.bucket_base;
+    uint64_t* off = as<uint64_t>(d.off) + j.off_base;
+    HIPCHECK(bucket_histogram(kin, j.n, j.nb, cnt, &jinfo[i].maxm, s));
+    HIPCHECK(scan_excl_u32(cnt, j.nb, off, as<uint64_t>(d.tmp), s));
+    HIPCHECK(bucket_scatter(kin, j.n, j.nb, off, as<uint32_t>(d.fill) + j.bucket_base,
+                            as<Key>(d.k0) + j.key_base, s));
   }
-  HIPCHECK(duplicate_check(as<Key>(d.k0), as<uint64_t>(d.off), nb, maxm, ctl, s));
-  HIPCHECK(node_counts(as<uint32_t>(d.cnt), nb, T->nodecnt, as<uint64_t>(d.nodes), s));
-  HIPCHECK(scan_excl_u64(as<uint64_t>(d.nodes), nb, as<uint64_t>(d.node_base), as<uint64_t>(d.tmp), s));
+  std::vector<JobInfo> hinfo(nj);
+  HIPCHECK(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(JobInfo), hipMemcpyDeviceToHost));
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    j.maxm = hinfo[i].maxm;
+    uint32_t p2 = 1;
+    while (p2 < j.maxm) p2 <<= 1;
+    // LDS of the duplicate check (next power of two) and of the search stage
+    if (j.maxm > kMaxBucketKeys || (uint64_t)p2 * 8 + 1024 > (uint64_t)d.lds_per_block)
+      j.status = RS_ERR_UNSUPPORTED;
+    if (j.status) continue;
+    const uint64_t* off = as<uint64_t>(d.off) + j.off_base;
+    HIPCHECK(duplicate_check(as<Key>(d.k0) + j.key_base, off, j.nb, j.maxm, &jinfo[i].error, s));
+    HIPCHECK(node_counts(as<uint32_t>(d.cnt) + j.bucket_base, j.nb, j.T->nodecnt,
+                         as<uint64_t>(d.nodes) + j.bucket_base, s));
+    HIPCHECK(scan_excl_u64(as<uint64_t>(d.nodes) + j.bucket_base, j.nb,
+                           as<uint64_t>(d.node_base) + j.off_base, as<uint64_t>(d.tmp), s));
+  }
+  HIPCHECK(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(JobInfo), hipMemcpyDeviceToHost));
   uint64_t total = 0;
-  HIPCHECK(hipMemcpy(&total, as<uint64_t>(d.node_base) + nb, sizeof total, hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(&h_ctl, ctl, sizeof h_ctl, hipMemcpyDeviceToHost));
-  if (h_ctl.error) return -(int)h_ctl.error;
+  uint32_t maxm = 0;
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    if (j.status) continue;
+    if (hinfo[i].error) {
+      j.status = -(int)hinfo[i].error;
+      continue;
+    }
+    HIPCHECK(hipMemcpy(&j.total, as<uint64_t>(d.node_base) + j.off_base + j.nb, sizeof(uint64_t),
+                       hipMemcpyDeviceToHost));
+    j.node_off = total;
+    total += j.total;
+    maxm = j.maxm > maxm ? j.maxm : maxm;
+  }
   if (total >= (1ull << 31)) return RS_ERR_UNSUPPORTED;
   HIPCHECK(hipEventRecord(d.ev[2], s));
 
-  // 2. seed search over all nodes
-  HIPCHECK(ensure(d.vals, total * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.msz, total * sizeof(uint32_t)));
+  // 2. seed search over all nodes of all jobs, one persistent launch
   uint32_t workers = 0;
   if (total) {
+    HIPCHECK(ensure(d.vals, total * sizeof(uint64_t)));
+    HIPCHECK(ensure(d.msz, total * sizeof(uint32_t)));
     HIPCHECK(ensure(d.tasks, total * sizeof(Task)));
     HIPCHECK(ensure(d.states, total * sizeof(TaskState)));
     HIPCHECK(ensure(d.ready_f, total * sizeof(uint32_t)));
@@ -331,28 +392,38 @@ int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint3
       if (w > 0 && (uint32_t)w < workers) workers = (uint32_t)w;
     }
     HIPCHECK(ensure(d.active, workers * sizeof(int32_t)));
-    HIPCHECK(ensure(d.jobs, sizeof(JobDev)));
-    HIPCHECK(fill_u64(as<uint64_t>(d.states), total * sizeof(TaskState) / 8, 0, s));
+    HIPCHECK(init_states(as<TaskState>(d.states), total, s));
     HIPCHECK(fill_u32(as<uint32_t>(d.ready_f), total, 0, s));
     HIPCHECK(fill_u32(as<uint32_t>(d.active), workers, 0xFFFFFFFFu, s));
-    HIPCHECK(init_states(as<TaskState>(d.states), total, s));
     HIPCHECK(hipMemcpy(&ctl->total, &total, sizeof(uint64_t), hipMemcpyHostToDevice));
-    JobDev job;
-    job.keys[0] = as<Key>(d.k0);
-    job.keys[1] = as<Key>(d.k1);
-    job.vals = as<uint64_t>(d.vals);
-    job.msz = as<uint32_t>(d.msz);
-    job.nodecnt = T->nodecnt;
-    job.tau = T->tau;
-    const Shape sh = make_shape(l);
-    job.l = sh.l;
-    job.la = sh.la;
-    job.ua = sh.ua;
-    job.rotation = rotation ? 1u : 0u;
-    HIPCHECK(hipMemcpy(d.jobs.p, &job, sizeof job, hipMemcpyHostToDevice));
-    HIPCHECK(queue_roots(as<uint32_t>(d.cnt), as<uint64_t>(d.off), as<uint64_t>(d.node_base), nb, 0,
-                         0, 0, as<Task>(d.tasks), as<uint32_t>(d.ready_f), ctl, s));
+    std::vector<JobDev> jd(nj);
+    for (uint32_t i = 0; i < nj; ++i) {
+      JobPlan& j = jobs[i];
+      JobDev& g = jd[i];
+      memset(&g, 0, sizeof g);
+      g.keys[0] = as<Key>(d.k0) + j.key_base;
+      g.keys[1] = as<Key>(d.k1) + j.key_base;
+      g.info = jinfo + i;
+      g.vals = as<uint64_t>(d.vals) + j.node_off;
+      g.msz = as<uint32_t>(d.msz) + j.node_off;
+      g.nodecnt = j.T->nodecnt;
+      g.tau = j.T->tau;
+      const Shape sh = make_shape(j.l);
+      g.l = sh.l;
+      g.la = sh.la;
+      g.ua = sh.ua;
+      g.rotation = (j.flags & RS_FLAG_ROTATION) ? 1u : 0u;
+    }
+    HIPCHECK(hipMemcpy(d.jobs.p, jd.data(), nj * sizeof(JobDev), hipMemcpyHostToDevice));
+    for (uint32_t i = 0; i < nj; ++i) {
+      JobPlan& j = jobs[i];
+      if (j.status || !j.total) continue;
+      HIPCHECK(queue_roots(as<uint32_t>(d.cnt) + j.bucket_base, as<uint64_t>(d.off) + j.off_base,
+                           as<uint64_t>(d.node_base) + j.off_base, j.nb, i, 0, 0, as<Task>(d.tasks),
+                           as<uint32_t>(d.ready_f), ctl, s));
+    }
     SearchParams P;
+    memset(&P, 0, sizeof P);
     P.jobs = as<JobDev>(d.jobs);
     P.tasks = as<Task>(d.tasks);
     P.states = as<TaskState>(d.states);
@@ -362,11 +433,10 @@ int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint3
     P.start = d.start;
     P.workers = workers;
     P.stage_cap = maxm;
-    const char* e1 = getenv("RS_ROUNDS_LEAF");
+    // rounds of 256 attempts per claimed chunk of a split search (a schedule
+    // setting: the result does not depend on it)
     const char* e2 = getenv("RS_ROUNDS_SPLIT");
-    P.rounds_leaf = e1 ? (uint32_t)atoi(e1) : 4u;
-    P.rounds_split = e2 ? (uint32_t)atoi(e2) : 8u;
-    if (P.rounds_leaf < 1) P.rounds_leaf = 1;
+    P.rounds_split = e2 ? (uint32_t)atoi(e2) : 16u;
     if (P.rounds_split < 1) P.rounds_split = 1;
     P.cap_shift = 10;
     P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
@@ -376,6 +446,7 @@ int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint3
     HIPCHECK(hipEventRecord(d.ev[3], s));
   }
   HIPCHECK(hipEventRecord(d.ev[4], s));
+  Control h_ctl;
   HIPCHECK(hipMemcpy(&h_ctl, ctl, sizeof h_ctl, hipMemcpyDeviceToHost));
   if (h_ctl.error && getenv("RS_DEBUG")) {
     fprintf(stderr,
@@ -385,59 +456,72 @@ int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint3
             h_ctl.dbg_m, h_ctl.dbg_depth, (unsigned long long)h_ctl.dbg_key_off,
             (unsigned long long)h_ctl.dbg_np, (unsigned long long)h_ctl.dbg_best,
             (unsigned long long)h_ctl.dbg_chunk, (unsigned long long)h_ctl.finished,
-            (unsigned long long)total, (unsigned long long)h_ctl.head, (unsigned long long)h_ctl.tail);
-    if (h_ctl.dbg_m && h_ctl.dbg_m <= kMaxBucketKeys && h_ctl.dbg_key_off + h_ctl.dbg_m <= n) {
-      std::vector<Key> hk(h_ctl.dbg_m);
-      const Key* src = (h_ctl.dbg_depth & 1) ? as<Key>(d.k1) : as<Key>(d.k0);
-      if (hipMemcpy(hk.data(), src + h_ctl.dbg_key_off, h_ctl.dbg_m * sizeof(Key),
-                    hipMemcpyDeviceToHost) == hipSuccess)
-        for (uint32_t i = 0; i < h_ctl.dbg_m; ++i)
-          fprintf(stderr, "[rs debug] key %u %016llx %016llx\n", i, (unsigned long long)hk[i].w0,
-                  (unsigned long long)hk[i].w1);
-    }
+            (unsigned long long)total, (unsigned long long)h_ctl.head,
+            (unsigned long long)h_ctl.tail);
   }
-  if (h_ctl.error) return -(int)h_ctl.error;
-  if (h_ctl.finished != total) return RS_ERR_DEVICE;
+  int search_rc = RS_OK;
+  if (h_ctl.error) search_rc = -(int)h_ctl.error;
+  else if (h_ctl.finished != total) search_rc = RS_ERR_DEVICE;
+  HIPCHECK(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(JobInfo), hipMemcpyDeviceToHost));
+  float ms_sort = 0, ms_search = 0;
+  (void)hipEventElapsedTime(&ms_sort, d.ev[1], d.ev[2]);
+  (void)hipEventElapsedTime(&ms_search, d.ev[3], d.ev[4]);
 
-  // 3. encode: record lengths, offsets P_j, then bits
-  if (total == 0) HIPCHECK(fill_u64(as<uint64_t>(d.len), nb, 0, s));
-  else
-    HIPCHECK(gr_lengths(as<uint64_t>(d.node_base), nb, as<uint64_t>(d.vals), as<uint32_t>(d.msz),
-                        T->tau, as<uint64_t>(d.len), s));
-  HIPCHECK(scan_excl_u64(as<uint64_t>(d.len), nb, as<uint64_t>(d.pos), as<uint64_t>(d.tmp), s));
+  // 3. encode every job that succeeded
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    if (j.status) continue;
+    if (search_rc) {
+      j.status = search_rc;
+      continue;
+    }
+    j.status = encode_job(d, j, hinfo[i], ms_sort, ms_search, workers, s);
+  }
+  return RS_OK;
+}
+
+int encode_job(Device& d, JobPlan& jp, const JobInfo& info, double ms_sort, double ms_search,
+               uint32_t workers, hipStream_t s) {
+  const uint64_t nb = jp.nb;
+  const uint64_t* node_base = as<uint64_t>(d.node_base) + jp.off_base;
+  const uint64_t* vals = as<uint64_t>(d.vals) + jp.node_off;
+  const uint32_t* msz = as<uint32_t>(d.msz) + jp.node_off;
+  uint64_t* len = as<uint64_t>(d.len) + jp.bucket_base;
+  uint64_t* pos = as<uint64_t>(d.pos) + jp.off_base;
+  HIPCHECK(hipEventRecord(d.ev[4], s));
+  if (jp.total == 0) HIPCHECK(fill_u64(len, nb, 0, s));
+  else HIPCHECK(gr_lengths(node_base, nb, vals, msz, jp.T->tau, len, s));
+  HIPCHECK(scan_excl_u64(len, nb, pos, as<uint64_t>(d.tmp), s));
   uint64_t gr_bits = 0;
-  HIPCHECK(hipMemcpy(&gr_bits, as<uint64_t>(d.pos) + nb, sizeof gr_bits, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(&gr_bits, pos + nb, sizeof gr_bits, hipMemcpyDeviceToHost));
 
   rs_mphf* f = new (std::nothrow) rs_mphf();
   if (!f) return RS_ERR_OOM;
-  f->n = n;
+  f->n = jp.n;
   f->nb = nb;
-  f->l = l;
-  f->b = b;
-  f->rotation = rotation ? 1u : 0u;
+  f->l = jp.l;
+  f->b = jp.b;
+  f->rotation = (jp.flags & RS_FLAG_ROTATION) ? 1u : 0u;
   f->device = d.id;
-  f->efc = ef_layout(nb + 1, n, kHeaderWords);
+  f->efc = ef_layout(nb + 1, jp.n, kHeaderWords);
   f->efp = ef_layout(nb + 1, gr_bits, f->efc.at + f->efc.words());
   f->gr_at = f->efp.at + f->efp.words();
   f->gr_bits = gr_bits;
   f->gr_words = (gr_bits + 63) / 64;
   const uint64_t nw = f->gr_at + 2 + f->gr_words;
-  hipError_t he = hipMalloc(&f->d_words, nw * sizeof(uint64_t));
-  if (he != hipSuccess) {
-    release(f);
-    return from_hip(he);
-  }
   auto fail = [&](int code) {
     release(f);
     return code;
   };
+  if (hipMalloc(&f->d_words, nw * sizeof(uint64_t)) != hipSuccess) {
+    f->d_words = nullptr;
+    return fail(RS_ERR_OOM);
+  }
   if (fill_u64(f->d_words, nw, 0, s) != hipSuccess) return fail(RS_ERR_DEVICE);
-  std::vector<uint64_t> hdr;
-  hdr.push_back(kMagic);
-  hdr.push_back(kVersion | ((uint64_t)f->rotation << 32));
-  hdr.push_back(n);
-  hdr.push_back((uint64_t)l | ((uint64_t)b << 32));
-  hdr.push_back(nb);
+  const uint64_t hdr[kHeaderWords] = {kMagic, kVersion | ((uint64_t)f->rotation << 32), jp.n,
+                                      (uint64_t)jp.l | ((uint64_t)jp.b << 32), nb};
+  if (hipMemcpy(f->d_words, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RS_ERR_DEVICE);
   const EFLayout* efs[2] = {&f->efc, &f->efp};
   for (int i = 0; i < 2; ++i) {
     const EFLayout& e = *efs[i];
@@ -446,14 +530,12 @@ int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint3
       return fail(RS_ERR_DEVICE);
   }
   const uint64_t gh[2] = {gr_bits, f->gr_words};
-  if (hipMemcpy(f->d_words, hdr.data(), hdr.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(f->d_words + f->gr_at, gh, sizeof gh, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpy(f->d_words + f->gr_at, gh, sizeof gh, hipMemcpyHostToDevice) != hipSuccess)
     return fail(RS_ERR_DEVICE);
   uint64_t* gr = f->d_words + f->gr_at + 2;
-  if (total && gr_write(as<uint64_t>(d.node_base), nb, as<uint64_t>(d.vals), as<uint32_t>(d.msz),
-                        T->tau, as<uint64_t>(d.pos), gr, s) != hipSuccess)
+  if (jp.total && gr_write(node_base, nb, vals, msz, jp.T->tau, pos, gr, s) != hipSuccess)
     return fail(RS_ERR_DEVICE);
-  const uint64_t* xs[2] = {as<uint64_t>(d.off), as<uint64_t>(d.pos)};
+  const uint64_t* xs[2] = {as<uint64_t>(d.off) + jp.off_base, pos};
   for (int i = 0; i < 2; ++i) {
     const EFLayout& e = *efs[i];
     if (ef_write(xs[i], e.N, (uint32_t)e.L, f->d_words + e.at + kEfHeaderWords,
@@ -464,39 +546,52 @@ int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint3
   f->words.resize(nw);
   if (hipMemcpy(f->words.data(), f->d_words, nw * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(RS_ERR_DEVICE);
-  rc = attach_device(d, f, true);
+  int rc = attach_device(d, f, true);
   if (rc) return fail(rc);
-
-  if (flags & RS_FLAG_KEEP_VALUES) {
-    f->keep_vals.resize(total);
+  if (jp.flags & RS_FLAG_KEEP_VALUES) {
+    f->keep_vals.resize(jp.total);
     f->keep_base.resize(nb + 1);
-    if ((total && hipMemcpy(f->keep_vals.data(), d.vals.p, total * 8, hipMemcpyDeviceToHost) != hipSuccess) ||
-        hipMemcpy(f->keep_base.data(), d.node_base.p, (nb + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    if ((jp.total && hipMemcpy(f->keep_vals.data(), vals, jp.total * 8, hipMemcpyDeviceToHost) !=
+                         hipSuccess) ||
+        hipMemcpy(f->keep_base.data(), node_base, (nb + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(RS_ERR_DEVICE);
   }
   rs_stats& st = f->stats;
   memset(&st, 0, sizeof st);
-  st.n = n;
+  st.n = jp.n;
   st.nb = nb;
-  st.nodes = total;
-  st.split_nodes = h_ctl.splits;
-  st.leaf_nodes = h_ctl.leaves;
-  st.useful_evals_split = h_ctl.evals_split;
-  st.useful_evals_leaf = h_ctl.evals_leaf;
+  st.nodes = jp.total;
+  st.split_nodes = info.splits;
+  st.leaf_nodes = info.leaves;
+  st.useful_evals_split = info.evals_split;
+  st.useful_evals_leaf = info.evals_leaf;
   st.gr_bits = gr_bits;
   st.bytes = nw * 8;
-  st.max_bucket = maxm;
+  st.max_bucket = jp.maxm;
   st.workers = workers;
   float ms = 0;
-  (void)hipEventElapsedTime(&ms, d.ev[1], d.ev[2]);
-  st.ms_sort = ms;
-  (void)hipEventElapsedTime(&ms, d.ev[3], d.ev[4]);
-  st.ms_search = ms;
+  st.ms_sort = ms_sort;
+  st.ms_search = ms_search;
   (void)hipEventElapsedTime(&ms, d.ev[4], d.ev[5]);
   st.ms_encode = ms;
   (void)hipEventElapsedTime(&ms, d.ev[0], d.ev[5]);
   st.ms_total = ms;
-  *out = f;
+  jp.out = f;
+  return RS_OK;
+}
+
+int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b,
+                 uint32_t flags, rs_mphf** out) {
+  std::vector<JobPlan> jobs(1);
+  jobs[0].keys = reinterpret_cast<const Key*>(keys);
+  jobs[0].n = n;
+  jobs[0].l = l;
+  jobs[0].b = b;
+  jobs[0].flags = flags;
+  int rc = build_jobs(d, jobs);
+  if (rc) return rc;
+  if (jobs[0].status) return jobs[0].status;
+  *out = jobs[0].out;
   return RS_OK;
 }
 
@@ -538,14 +633,17 @@ int parse(const uint64_t* w, uint64_t nw, rs_mphf* f) {
 
 extern "C" {
 
+static bool job_args_ok(const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b, uint32_t flags) {
+  return l >= 2 && l <= kMaxLeaf && b >= 1 && b <= RS_MAX_BUCKET_SIZE && n < (1ull << 40) &&
+         (!n || keys) &&
+         !(flags & ~(uint32_t)(RS_FLAG_ROTATION | RS_FLAG_KEYS_ON_DEVICE | RS_FLAG_KEEP_VALUES));
+}
+
 int rs_build(const rs_key128* keys, uint64_t n, uint32_t leaf_size, uint32_t bucket_size,
              uint32_t flags, rs_mphf** out) {
   if (!out) return RS_ERR_INVALID_ARG;
   *out = nullptr;
-  if (leaf_size < 2 || leaf_size > kMaxLeaf || bucket_size < 1 || bucket_size > RS_MAX_BUCKET_SIZE ||
-      n >= (1ull << 40) || (n && !keys) ||
-      (flags & ~(uint32_t)(RS_FLAG_ROTATION | RS_FLAG_KEYS_ON_DEVICE | RS_FLAG_KEEP_VALUES)))
-    return RS_ERR_INVALID_ARG;
+  if (!job_args_ok(keys, n, leaf_size, bucket_size, flags)) return RS_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lock(g_mu);
   Device* d = nullptr;
   int rc = device_init(&d);
@@ -557,6 +655,53 @@ int rs_build(const rs_key128* keys, uint64_t n, uint32_t leaf_size, uint32_t buc
     (void)hipGetLastError();
   }
   return rc;
+}
+
+int rs_build_batch(const rs_job* jobs, uint32_t njobs, rs_mphf** outs, int* statuses) {
+  if ((njobs && (!jobs || !outs || !statuses)) || njobs > 65535) return RS_ERR_INVALID_ARG;
+  std::vector<JobPlan> plan;
+  std::vector<uint32_t> index;
+  for (uint32_t i = 0; i < njobs; ++i) {
+    outs[i] = nullptr;
+    const rs_job& j = jobs[i];
+    if (!job_args_ok(j.keys, j.n, j.leaf_size, j.bucket_size, j.flags)) {
+      statuses[i] = RS_ERR_INVALID_ARG;
+      continue;
+    }
+    statuses[i] = RS_OK;
+    JobPlan p;
+    p.keys = reinterpret_cast<const Key*>(j.keys);
+    p.n = j.n;
+    p.l = j.leaf_size;
+    p.b = j.bucket_size;
+    p.flags = j.flags;
+    plan.push_back(p);
+    index.push_back(i);
+  }
+  int first = RS_OK;
+  if (!plan.empty()) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    Device* d = nullptr;
+    int rc = device_init(&d);
+    if (!rc) rc = build_jobs(*d, plan);
+    if (rc) {
+      (void)hipDeviceSynchronize();
+      (void)hipGetLastError();
+    }
+    for (size_t k = 0; k < plan.size(); ++k) {
+      if (rc) {
+        release(plan[k].out);
+        plan[k].out = nullptr;
+        plan[k].status = rc;
+      }
+      statuses[index[k]] = plan[k].status;
+      outs[index[k]] = plan[k].status ? nullptr : plan[k].out;
+      if (plan[k].status && plan[k].out) release(plan[k].out);
+    }
+  }
+  for (uint32_t i = 0; i < njobs; ++i)
+    if (statuses[i] && !first) first = statuses[i];
+  return first;
 }
 
 int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out, uint32_t flags) {

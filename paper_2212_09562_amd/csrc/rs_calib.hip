@@ -113,10 +113,16 @@ extern "C" int rs_calibrate_valu(rs_valu_rates* out) {
   s[7] = time_kernel(k_calib<7>, blocks, iters, buf);
   const uint32_t hiters = 2048;
   const double sh = time_kernel(k_calib_hash, blocks, hiters, buf);
+  // the same loop for about two seconds: the clock the chip holds under a
+  // sustained full-occupancy integer load
+  const double per_iter = sh / hiters;
+  uint32_t long_iters = per_iter > 0 ? (uint32_t)(2.0 / per_iter) : 0;
+  if (long_iters < hiters) long_iters = hiters;
+  const double sl = time_kernel(k_calib_hash, blocks, long_iters, buf);
   (void)hipFree(buf);
   for (double v : s)
     if (v <= 0) return RS_ERR_DEVICE;
-  if (sh <= 0) return RS_ERR_DEVICE;
+  if (sh <= 0 || sl <= 0) return RS_ERR_DEVICE;
   out->add_u32 = per / s[0];
   out->xor_b32 = per / s[1];
   out->mul_lo_u32 = per / s[2];
@@ -126,6 +132,7 @@ extern "C" int rs_calibrate_valu(rs_valu_rates* out) {
   out->lshl_add_u64 = per / s[6];
   out->add3_u32 = per / s[7];
   out->hash_evals = lanes * hiters * 16.0 / sh;
+  out->hash_evals_sustained = lanes * (double)long_iters * 16.0 / sl;
   out->compute_units = (uint32_t)cus;
   return RS_OK;
 }

@@ -122,8 +122,17 @@ struct TaskState {
   uint64_t pad1;
 };
 
+// Per-job results the kernels write: largest bucket, first error, and the
+// useful work of the search (hash evaluations the sequential definition makes).
+struct JobInfo {
+  uint32_t maxm;
+  uint32_t error;
+  uint64_t evals_split, evals_leaf, splits, leaves;
+};
+
 struct JobDev {
   Key* keys[2];             // ping-pong key arrays: depth d reads keys[d & 1]
+  JobInfo* info;
   uint64_t* vals;           // node values
   uint32_t* msz;            // node sizes
   const uint32_t* nodecnt;  // stored nodes of a subtree of size m
@@ -137,10 +146,8 @@ struct Control {
   uint64_t tail;      // next queue slot to fill
   uint64_t finished;  // nodes whose value is final
   uint64_t total;     // nodes of all jobs
-  uint32_t error;     // first RS_ERR_* seen by a kernel (as a positive number)
-  uint32_t maxm;      // largest bucket
-  uint64_t evals_split, evals_leaf;  // useful hash evaluations
-  uint64_t splits, leaves;
+  uint32_t error;     // first RS_ERR_* seen by the search (as a positive number)
+  uint32_t pad;
   // the node that raised the first error (diagnostics)
   uint64_t dbg_key_off, dbg_node, dbg_slot, dbg_np, dbg_best, dbg_chunk;
   uint32_t dbg_m, dbg_depth;
@@ -156,7 +163,7 @@ struct SearchParams {
   const uint64_t* start;  // starting seed per depth
   uint32_t workers;
   uint32_t stage_cap;  // keys staged in LDS per worker
-  uint32_t rounds_leaf, rounds_split;
+  uint32_t rounds_split;  // rounds of 256 attempts per claimed split chunk
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
 };

@@ -13,12 +13,12 @@ uint64_t scan_tmp_words(uint64_t n);
 hipError_t scan_excl_u32(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
 hipError_t scan_excl_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
 
-hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, Control* ctl,
+hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, uint32_t* maxm,
                             hipStream_t s);
 hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
                           uint32_t* fill, Key* out, hipStream_t s);
 hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t maxm,
-                           Control* ctl, hipStream_t s);
+                           uint32_t* error, hipStream_t s);
 hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s);
 hipError_t node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* nodecnt, uint64_t* out,
                        hipStream_t s);

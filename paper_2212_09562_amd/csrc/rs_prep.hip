@@ -123,13 +123,13 @@ __global__ void k_hist(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, 
   }
 }
 
-__global__ void k_max_bucket(const uint32_t* cnt, uint64_t nb, Control* ctl) {
+__global__ void k_max_bucket(const uint32_t* cnt, uint64_t nb, uint32_t* maxm) {
   uint32_t mx = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nb;
        i += (uint64_t)gridDim.x * blockDim.x)
     mx = max(mx, cnt[i]);
   for (uint32_t d = 32; d > 0; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d));
-  if ((threadIdx.x & 63) == 0) atomicMax(&ctl->maxm, mx);
+  if ((threadIdx.x & 63) == 0) atomicMax(maxm, mx);
 }
 
 __global__ void k_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
@@ -146,7 +146,7 @@ __global__ void k_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64
 // leaf could never be a bijection: sort the bucket's w1 words (bitonic, in
 // LDS) and compare neighbours.
 __global__ void __launch_bounds__(256) k_dupcheck(const Key* keys, const uint64_t* off, uint64_t nb,
-                                                  Control* ctl) {
+                                                  uint32_t* error) {
   extern __shared__ uint64_t s[];
   for (uint64_t j = blockIdx.x; j < nb; j += gridDim.x) {
     const uint64_t o = off[j];
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_dupcheck(const Key* keys, const uint64_
     }
     bool dup = false;
     for (uint32_t i = threadIdx.x; i + 1 < m; i += blockDim.x) dup |= s[i] == s[i + 1];
-    if (dup) atomicCAS(&ctl->error, 0u, (uint32_t)(-RS_ERR_DUPLICATE));
+    if (dup) atomicCAS(error, 0u, (uint32_t)(-RS_ERR_DUPLICATE));
     __syncthreads();
   }
 }
@@ -261,7 +261,7 @@ hipError_t scan_excl_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t
   return scan_impl<uint64_t>(in, n, out, tmp, s);
 }
 
-hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, Control* ctl,
+hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, uint32_t* maxm,
                             hipStream_t s) {
   if (n) {
     const bool lds = nb <= 16384;
@@ -269,7 +269,7 @@ hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* 
     k_hist<<<grid, 256, lds ? (uint32_t)(nb * sizeof(uint32_t)) : 0, s>>>(keys, n, nb, cnt,
                                                                           lds ? 1u : 0u);
   }
-  k_max_bucket<<<grid_for(nb, 256, 1024), 256, 0, s>>>(cnt, nb, ctl);
+  k_max_bucket<<<grid_for(nb, 256, 1024), 256, 0, s>>>(cnt, nb, maxm);
   return hipGetLastError();
 }
 
@@ -281,11 +281,11 @@ hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64
 }
 
 hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t maxm,
-                           Control* ctl, hipStream_t s) {
+                           uint32_t* error, hipStream_t s) {
   if (maxm < 2) return hipSuccess;
   uint32_t p2 = 1;
   while (p2 < maxm) p2 <<= 1;
-  k_dupcheck<<<grid_for(nb, 1, 4096), 256, p2 * sizeof(uint64_t), s>>>(keys, off, nb, ctl);
+  k_dupcheck<<<grid_for(nb, 1, 4096), 256, p2 * sizeof(uint64_t), s>>>(keys, off, nb, error);
   return hipGetLastError();
 }
 

@@ -339,9 +339,9 @@ __device__ void finalize_split(const SearchParams& P, const Task& t, const JobDe
     if (!all_good) set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
     J.vals[t.node] = s;
     J.msz[t.node] = c.m;
-    __hip_atomic_fetch_add(&P.ctl->evals_split, (s + 1) * c.m, __ATOMIC_RELAXED,
+    __hip_atomic_fetch_add(&J.info->evals_split, (s + 1) * c.m, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&P.ctl->splits, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&J.info->splits, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t child_node = t.node + 1;
     for (uint32_t j = 0; j < c.k; ++j) {
       const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
@@ -375,24 +375,31 @@ __device__ void finalize_leaf(const SearchParams& P, const Task& t, const JobDev
     J.vals[t.node] = v;
     J.msz[t.node] = c.m;
     const uint64_t att = c.rotation ? v / c.m : v;
-    __hip_atomic_fetch_add(&P.ctl->evals_leaf, (att + 1) * c.m, __ATOMIC_RELAXED,
+    __hip_atomic_fetch_add(&J.info->evals_leaf, (att + 1) * c.m, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&P.ctl->leaves, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&J.info->leaves, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 // Drop one in-flight chunk of task st; returns true for the one caller that
 // must finalize (the task has a value and nothing is in flight any more).
+// Relaxed agent-scope atomics: the value and the counters share one cache line
+// of the task state, every such atomic is performed at the device coherence
+// point, and a caller that published a value waited for that atomic to
+// complete before dropping its chunk, so whoever sees the count reach zero
+// also sees the value.
 __device__ __forceinline__ bool release_chunk(TaskState* st) {
   const uint64_t old =
-      __hip_atomic_fetch_add(&st->np, ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&st->np, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if ((old & 0xFFFFFFFFull) != 1) return false;
-  if (ld_acquire(&st->best) == kInf) return false;
+  if (ld_relaxed(&st->best) == kInf) return false;
   uint32_t expected = 0;
-  return __hip_atomic_compare_exchange_strong(&st->closed, &expected, 1u, __ATOMIC_ACQ_REL,
+  return __hip_atomic_compare_exchange_strong(&st->closed, &expected, 1u, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 struct Shared {
   Task task;
@@ -424,9 +431,27 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   stage_keys(t, J, c, s_keys, &sh.na);
   __syncthreads();
   if (c.kind == kLeaf) c.na = uni(sh.na);
-  const uint32_t rounds = c.kind == kLeaf ? P.rounds_leaf
-                        : c.kind == kBinary ? 1u
-                                            : P.rounds_split;
+  if (c.kind == kLeaf) {
+    // A leaf is short and there are many: its owner searches it alone, as one
+    // chunk without a bound on its rounds, with no global traffic until the
+    // value is known.  Nobody joins a leaf (its state is never claimed).
+    if (tid == 0) sh.best = kInf;
+    __syncthreads();
+    const uint64_t max_rounds = c.cap / kWG + 1;
+    eval_chunk(s_keys, c, 0, max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu,
+               &sh.best);
+    __syncthreads();
+    const uint64_t v = sh.best;
+    if (v == kInf) {
+      if (tid == 0 && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
+        record_failure(P.ctl, t, slot, P.states + slot, 0);
+    } else {
+      finalize_leaf(P, t, J, c, v);
+    }
+    __syncthreads();
+    return;
+  }
+  const uint32_t rounds = c.kind == kBinary ? 1u : P.rounds_split;
   const uint64_t per_chunk = (uint64_t)rounds * kWG;
   TaskState* st = P.states + slot;
   for (;;) {
@@ -436,13 +461,13 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       uint64_t chunk = kStop;
       if (ld_relaxed(&P.ctl->error) != 0) {
         chunk = kStop;
-      } else if (!own && my_q < kExhausted && ld_acquire(&P.ready[my_q]) != 0) {
+      } else if (!own && my_q < kExhausted && ld_relaxed(&P.ready[my_q]) != 0) {
         chunk = kStop;
       } else {
         const uint64_t old = __hip_atomic_fetch_add(&st->np, (1ull << 32) | 1ull,
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t ci = old >> 32;
-        const uint64_t best = ld_acquire(&st->best);
+        const uint64_t best = ld_relaxed(&st->best);
         const uint64_t first = ci * per_chunk;
         // every worker may hold one claimed chunk whose result is not in yet
         if (first >= c.cap + (uint64_t)P.workers * per_chunk) {
@@ -463,18 +488,19 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       eval_chunk(s_keys, c, chunk, rounds, &sh.best);
       __syncthreads();
       if (tid == 0) {
-        if (sh.best != kInf)
+        if (sh.best != kInf) {
           __hip_atomic_fetch_min(&st->best, sh.best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wait_memory();  // the value is in before the chunk is dropped
+        }
         sh.fin = release_chunk(st) ? 1u : 0u;
       }
       __syncthreads();
     }
     if (sh.fin) {
-      if (tid == 0) sh.fin_value = ld_acquire(&st->best);
+      if (tid == 0) sh.fin_value = ld_relaxed(&st->best);
       __syncthreads();
       const uint64_t v = sh.fin_value;
-      if (c.kind == kLeaf) finalize_leaf(P, t, J, c, v);
-      else if (tid < 64) finalize_split(P, t, J, c, v);
+      if (tid < 64) finalize_split(P, t, J, c, v);
       __syncthreads();
       return;
     }

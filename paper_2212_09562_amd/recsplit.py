@@ -55,7 +55,8 @@ class ValuRates(ctypes.Structure):
                 ("mul_lo_u32", ctypes.c_double), ("mul_hi_u32", ctypes.c_double),
                 ("mad_u64_u32", ctypes.c_double), ("lshrrev_b64", ctypes.c_double),
                 ("lshl_add_u64", ctypes.c_double), ("add3_u32", ctypes.c_double),
-                ("hash_evals", ctypes.c_double), ("compute_units", ctypes.c_uint32)]
+                ("hash_evals", ctypes.c_double), ("hash_evals_sustained", ctypes.c_double),
+                ("compute_units", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,13 +76,20 @@ _lib.rs_serialize.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64)]
 _lib.rs_deserialize.argtypes = [_vp, _u64, ctypes.POINTER(_vp)]
 _lib.rs_debug_node_values.argtypes = [_vp, _u64, _vp, _u64, ctypes.POINTER(_u64)]
 _lib.rs_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+class Job(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("n", ctypes.c_uint64), ("leaf_size", ctypes.c_uint32),
+                ("bucket_size", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+_lib.rs_build_batch.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(_vp),
+                                ctypes.POINTER(ctypes.c_int)]
 _lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
 _lib.rs_free.argtypes = [_vp]
 _lib.rs_free.restype = None
 _lib.rs_strerror.argtypes = [ctypes.c_int]
 _lib.rs_strerror.restype = ctypes.c_char_p
-for _f in ("rs_build", "rs_query", "rs_serialize", "rs_deserialize", "rs_debug_node_values",
-           "rs_get_stats", "rs_calibrate_valu"):
+for _f in ("rs_build", "rs_build_batch", "rs_query", "rs_serialize", "rs_deserialize",
+           "rs_debug_node_values", "rs_get_stats", "rs_calibrate_valu"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -161,6 +169,25 @@ def build(keys, leaf_size: int, bucket_size: int, rotation: bool = True,
     h = ctypes.c_void_p()
     _check(_lib.rs_build(ptr, n, leaf_size, bucket_size, flags, ctypes.byref(h)), "rs_build")
     return MPHF(h.value)
+
+
+def build_batch(jobs):
+    """rs_build_batch: jobs is a sequence of dicts with keys, leaf_size,
+    bucket_size and optionally rotation (default True) and keep_values.
+    Returns (list of MPHF or None, list of status codes)."""
+    arr = (Job * max(len(jobs), 1))()
+    keep = []
+    for i, j in enumerate(jobs):
+        ptr, n, flags, k = _keys_arg(j["keys"])
+        keep.append(k)
+        flags |= RS_FLAG_ROTATION if j.get("rotation", True) else 0
+        flags |= RS_FLAG_KEEP_VALUES if j.get("keep_values", False) else 0
+        arr[i] = Job(ptr, n, j["leaf_size"], j["bucket_size"], flags)
+    outs = (ctypes.c_void_p * max(len(jobs), 1))()
+    st = (ctypes.c_int * max(len(jobs), 1))()
+    _lib.rs_build_batch(arr, len(jobs), outs, st)
+    res = [MPHF(outs[i]) if outs[i] else None for i in range(len(jobs))]
+    return res, [int(st[i]) for i in range(len(jobs))]
 
 
 def deserialize(data: bytes) -> MPHF:

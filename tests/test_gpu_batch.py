@@ -1,0 +1,91 @@
+"""GPU: many key sets in one persistent launch (rs_build_batch).
+
+Every job's result must be the same bytes as its solo build and as the
+oracle's; a job that fails (duplicate keys, arguments out of range) reports
+its own code and leaves the others untouched.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_09562_amd import keygen
+
+pytestmark = pytest.mark.gpu
+
+
+def rs():
+    from paper_2212_09562_amd import recsplit
+
+    return recsplit
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def test_mixed_batch_matches_solo_and_oracle():
+    import torch
+
+    _case("mixed batch of 9 jobs")
+    specs = [(5000, 8, 100, True), (0, 8, 100, True), (1, 5, 7, False), (20000, 12, 500, True),
+             (3000, 4, 30, False), (7000, 6, 1, True), (12000, 8, 4096, True), (4000, 16, 2000, True),
+             (2500, 3, 50, True)]
+    jobs, wants = [], []
+    for i, (n, l, b, rot) in enumerate(specs):
+        keys = keygen.fingerprints(n, 700 + i)
+        dev = i % 2 == 1
+        jobs.append({"keys": torch.from_numpy(keys.view(np.int64)).cuda() if dev else keys,
+                     "leaf_size": l, "bucket_size": b, "rotation": rot, "host": keys})
+        wants.append(oracle.build(keys, l, b, rot)[0])
+    # a duplicate and a bad argument in the middle of the batch
+    dup = keygen.fingerprints(3000, 799)
+    dup[3, 1] = dup[4, 1]
+    dup[3, 0] = dup[4, 0] ^ np.uint64(1)
+    jobs.insert(4, {"keys": dup, "leaf_size": 8, "bucket_size": 100, "rotation": True})
+    jobs.insert(6, {"keys": keygen.fingerprints(10, 798), "leaf_size": 30, "bucket_size": 100})
+    outs, st = rs().build_batch(jobs)
+    assert st[4] == -2 and outs[4] is None
+    assert st[6] == -1 and outs[6] is None
+    k = 0
+    for i, j in enumerate(jobs):
+        if i in (4, 6):
+            continue
+        assert st[i] == 0, (i, st[i])
+        got = outs[i].serialize()
+        assert got == wants[k], i
+        solo = rs().build(j["host"], j["leaf_size"], j["bucket_size"], j["rotation"]).serialize()
+        assert got == solo
+        r = outs[i].query(j["host"])
+        assert np.array_equal(r, oracle.query(wants[k], j["host"]))
+        k += 1
+
+
+def test_batched_configuration_same_as_solo():
+    """The 64-set batch (sizes log-uniform in [10^3, 10^6], l in {8,12,16}, b in
+    {100,500,2000}, seed 4): every set's bytes equal its solo build, the ranks of
+    every set form a permutation, and the oracle agrees on the small sets and on
+    sampled buckets of the large ones."""
+    import torch
+
+    jobs = keygen.batched_jobs(64, seed=4)
+    _case(f"64-job batch, {sum(j['n'] for j in jobs)} keys")
+    batch = [{"keys": torch.from_numpy(j["keys"].view(np.int64)).cuda(), "leaf_size": j["leaf_size"],
+              "bucket_size": j["bucket_size"], "keep_values": True} for j in jobs]
+    outs, st = rs().build_batch(batch)
+    assert all(s == 0 for s in st), st
+    sampled = 0
+    for i, j in enumerate(jobs):
+        data = outs[i].serialize()
+        solo = rs().build(batch[i]["keys"], j["leaf_size"], j["bucket_size"], True).serialize()
+        assert data == solo, i
+        r = outs[i].query(batch[i]["keys"])
+        assert torch.equal(torch.sort(r)[0], torch.arange(j["n"], device=r.device, dtype=r.dtype))
+        cheap = (j["leaf_size"] == 8 and j["n"] <= 300000) or \
+            (j["leaf_size"] == 12 and j["n"] <= 20000) or j["n"] <= 2000
+        if cheap:
+            assert data == oracle.build(j["keys"], j["leaf_size"], j["bucket_size"], True)[0], i
+        elif sampled < 4 and j["bucket_size"] <= 500:
+            sampled += 1
+            recs, _ = oracle.build_buckets(j["keys"], j["leaf_size"], j["bucket_size"], True, [0])
+            for (bk, size, vals, words, nbits) in recs:
+                assert np.array_equal(outs[i].node_values(bk), vals), (i, bk)

@@ -94,10 +94,10 @@ def test_device_keys_and_determinism():
     assert np.array_equal(r.cpu().numpy().view(np.uint64), oracle.query(want, keys))
     # a shuffled copy and a different chunk schedule give the same bytes
     perm = np.random.default_rng(0).permutation(len(keys))
-    old = {k: os.environ.get(k) for k in ("RS_ROUNDS_LEAF", "RS_ROUNDS_SPLIT")}
+    old = {k: os.environ.get(k) for k in ("RS_ROUNDS_SPLIT", "RS_WORKERS")}
     try:
-        os.environ["RS_ROUNDS_LEAF"] = "1"
         os.environ["RS_ROUNDS_SPLIT"] = "3"
+        os.environ["RS_WORKERS"] = "37"
         assert rs().build(keys[perm], 8, 100, True).serialize() == want
     finally:
         for k, v in old.items():
