@@ -35,6 +35,7 @@ typedef struct rs_mphf rs_mphf;
 
 enum {
   RS_OK = 0,
+  RS_PENDING = 1,           /* rs_server_poll: the request is not finished yet */
   RS_ERR_INVALID_ARG = -1,  /* leaf size, bucket size, n or a pointer out of range */
   RS_ERR_DUPLICATE = -2,    /* two keys of one bucket share w1: no bijection exists */
   RS_ERR_OOM = -3,          /* device or host allocation failed */
@@ -62,8 +63,9 @@ enum {
  * Golomb-Rice and Elias-Fano encoding).
  *
  * keys:        n rs_key128, host memory, or device memory with
- *              RS_FLAG_KEYS_ON_DEVICE (read on the null stream, which orders
- *              after work on the legacy default stream).  Read only.
+ *              RS_FLAG_KEYS_ON_DEVICE (read on the library's own stream,
+ *              ordered after the work queued so far on the legacy default
+ *              stream; work on other streams must be complete).  Read only.
  * n:           0 <= n < 2^40.
  * leaf_size:   l, 2 <= l <= 24.
  * bucket_size: b, the expected bucket size, 1 <= b <= 4096; nb = max(1, ceil(n/b)).
@@ -96,6 +98,71 @@ typedef struct {
 } rs_job;
 
 int rs_build_batch(const rs_job *jobs, uint32_t njobs, rs_mphf **outs, int *statuses);
+
+/*
+ * Construction server: continuous batching of build requests on one device
+ * under a fixed HBM budget (a serving form of rs_build_batch).
+ *
+ * rs_server_create allocates one device pool of hbm_budget_bytes and starts
+ * max_slots host threads, each with its own non-blocking HIP stream.
+ * Requests queue in arrival order; a free slot takes the oldest waiting
+ * requests whose combined working memory fits one free region of the pool
+ * (up to max_jobs_per_launch of them), builds them together exactly as
+ * rs_build_batch does (one persistent search launch), and frees the region.
+ * Slots run concurrently, so newly arrived requests are admitted while
+ * earlier ones are still on the device and their kernels overlap.  A request
+ * whose own working memory exceeds the budget is refused at submission
+ * (RS_ERR_OOM).  The result of every request is identical to rs_build of
+ * that request alone.
+ *
+ * Key arrays passed to rs_server_submit (host, or device with
+ * RS_FLAG_KEYS_ON_DEVICE) are read when the request is admitted and must
+ * stay valid and unchanged until rs_server_poll returns its result; device
+ * keys must be complete before submission (the slot's stream orders only
+ * after the legacy default stream).  All entry points are thread
+ * safe, except that no call may overlap rs_server_destroy, which waits for
+ * the builds in progress, drops requests not yet admitted, and frees results
+ * never collected.  The server runs on the device current at creation.
+ */
+typedef struct rs_server rs_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes;    /* device pool size, >= 1 MiB */
+  uint32_t max_slots;           /* concurrent builds, 1..64 */
+  uint32_t max_jobs_per_launch; /* requests per search launch, >= 1 */
+} rs_server_config;
+
+typedef struct {
+  double submit, admit, done; /* host steady-clock seconds */
+  uint32_t slot;              /* slot that built the request */
+  uint32_t batch_jobs;        /* requests in its launch */
+} rs_request_times;
+
+typedef struct {
+  uint64_t submitted, completed, launches, keys_completed;
+  uint64_t waiting, bytes_in_use, peak_bytes;
+} rs_server_stats;
+
+int rs_server_create(const rs_server_config *cfg, rs_server **out);
+
+/* Queue one build; *ticket names it for rs_server_poll.  RS_ERR_INVALID_ARG
+ * for arguments rs_build would refuse; RS_ERR_OOM when it can never fit. */
+int rs_server_submit(rs_server *s, const rs_job *job, uint64_t *ticket);
+
+/*
+ * Result of a request.  With wait = 0 returns RS_PENDING while the request is
+ * queued or running; otherwise (or with wait != 0, after blocking until it
+ * ends) returns RS_OK, sets *status to the build's code and *out to its
+ * structure (NULL when the build failed; the caller releases it with
+ * rs_free), fills *times when times is not NULL, and forgets the ticket.
+ * RS_ERR_INVALID_ARG for an unknown or already collected ticket.
+ */
+int rs_server_poll(rs_server *s, uint64_t ticket, int wait, rs_mphf **out, int *status,
+                   rs_request_times *times);
+
+int rs_server_get_stats(rs_server *s, rs_server_stats *st);
+
+void rs_server_destroy(rs_server *s);
 
 /*
  * Evaluate the function on n keys (Sec. 2.2 "Query": bucket, tree descent,

@@ -2,6 +2,11 @@
 // kernel orchestration, serialisation.  Every step of the construction and
 // of queries runs in the kernels of rs_prep.hip, rs_search.hip and
 // rs_encode.hip; this file only launches them and moves results.
+//
+// Work runs on per-context non-blocking streams, so several builds (the
+// construction server's slots) overlap on the device.  Before touching
+// caller data a context waits for the work already queued on the legacy
+// default stream (where torch puts its kernels unless told otherwise).
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -10,7 +15,7 @@
 #include <mutex>
 #include <vector>
 
-#include "rs_launch.h"
+#include "rs_host.h"
 
 using namespace rs;
 
@@ -20,41 +25,18 @@ constexpr uint64_t kMagic = 0x31564C5053434552ull;  // "RECSPLV1"
 constexpr uint64_t kVersion = 1;
 constexpr uint32_t kHeaderWords = 5;
 constexpr uint32_t kEfHeaderWords = 6;
+constexpr size_t kAlign = 256;
 
-struct Buffer {
-  void* p = nullptr;
-  size_t cap = 0;
-};
-
-hipError_t ensure(Buffer& b, size_t bytes) {
-  if (bytes == 0) bytes = 8;
-  if (b.cap >= bytes) return hipSuccess;
-  if (b.p) (void)hipFree(b.p);
-  b.p = nullptr;
-  b.cap = 0;
-  size_t want = bytes + bytes / 4;
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return e;
-  }
-  b.cap = want;
-  return hipSuccess;
+int from_hip(hipError_t e) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return RS_ERR_OOM;
+  return e == hipSuccess ? RS_OK : RS_ERR_DEVICE;
 }
 
-template <typename T>
-T* as(Buffer& b) {
-  return static_cast<T*>(b.p);
-}
-
-// Per-leaf-size tables, m = 0 .. kMaxBucketKeys: stored nodes of a subtree,
-// Golomb-Rice fixed bits of a subtree, and the Rice parameter of a node.
-struct Tables {
-  uint32_t* nodecnt = nullptr;
-  uint32_t* fixedbits = nullptr;
-  uint8_t* tau = nullptr;
-  std::vector<uint32_t> h_nodecnt;
-};
+#define HIPCHECK(expr)                         \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
 
 // log of the probability that one trial succeeds at a node of size m: a leaf
 // is a bijection with probability m!/m^m; a split hits its part sizes p_j
@@ -107,72 +89,28 @@ uint64_t splitmix_next(uint64_t& state) {
   return mix64(state);
 }
 
-struct Device {
-  bool ready = false;
-  int id = 0;
-  int cus = 0;
-  int wall_khz = 100000;
-  int lds_per_block = 65536;
-  uint64_t* start = nullptr;  // starting seed of depth d: SplitMix64(0) output d+1
-  Tables tables[kMaxLeaf + 1];
-  Buffer keys_in, k0, k1, cnt, fill, off, tmp, nodes, node_base, vals, msz, tasks, states, ready_f,
-      active, ctl, jobs, jinfo, len, pos, qkeys, qout, sc_counts, sc_prefix;
-  hipEvent_t ev[6];
-};
-
-std::mutex g_mu;
 Device g_dev[64];
-
-int from_hip(hipError_t e) {
-  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return RS_ERR_OOM;
-  return e == hipSuccess ? RS_OK : RS_ERR_DEVICE;
-}
-
-#define HIPCHECK(expr)                     \
-  do {                                     \
-    hipError_t e_ = (expr);                \
-    if (e_ != hipSuccess) return from_hip(e_); \
-  } while (0)
-
-int device_init(Device** out) {
-  int id = 0;
-  HIPCHECK(hipGetDevice(&id));
-  if (id < 0 || id >= 64) return RS_ERR_DEVICE;
-  Device& d = g_dev[id];
-  if (!d.ready) {
-    d.id = id;
-    HIPCHECK(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, id));
-    if (hipDeviceGetAttribute(&d.lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, id) !=
-            hipSuccess ||
-        d.lds_per_block <= 0)
-      d.lds_per_block = 65536;
-    if (hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, id) != hipSuccess ||
-        d.wall_khz <= 0)
-      d.wall_khz = 100000;
-    uint64_t h[kMaxDepth], st = 0;
-    for (uint32_t i = 0; i < kMaxDepth; ++i) h[i] = splitmix_next(st);
-    HIPCHECK(hipMalloc(&d.start, sizeof h));
-    HIPCHECK(hipMemcpy(d.start, h, sizeof h, hipMemcpyHostToDevice));
-    for (int i = 0; i < 6; ++i) HIPCHECK(hipEventCreate(&d.ev[i]));
-    d.ready = true;
-  }
-  *out = &d;
-  return RS_OK;
-}
+std::mutex g_devices_mu;
+Context g_default[64];
 
 int tables_for(Device& d, uint32_t l, Tables** out) {
+  std::lock_guard<std::mutex> lock(d.mu);
   Tables& t = d.tables[l];
   if (!t.nodecnt) {
     std::vector<uint32_t> nc, fb;
     std::vector<uint8_t> tau;
     compute_tables(l, nc, fb, tau);
-    HIPCHECK(hipMalloc(&t.nodecnt, kTable * sizeof(uint32_t)));
-    HIPCHECK(hipMalloc(&t.fixedbits, kTable * sizeof(uint32_t)));
-    HIPCHECK(hipMalloc(&t.tau, kTable));
-    HIPCHECK(hipMemcpy(t.nodecnt, nc.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(t.fixedbits, fb.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(t.tau, tau.data(), kTable, hipMemcpyHostToDevice));
-    t.h_nodecnt = nc;
+    uint32_t *a = nullptr, *b = nullptr;
+    uint8_t* c = nullptr;
+    HIPCHECK(hipMalloc(&a, kTable * sizeof(uint32_t)));
+    HIPCHECK(hipMalloc(&b, kTable * sizeof(uint32_t)));
+    HIPCHECK(hipMalloc(&c, kTable));
+    HIPCHECK(hipMemcpy(a, nc.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b, fb.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(c, tau.data(), kTable, hipMemcpyHostToDevice));
+    t.fixedbits = b;
+    t.tau = c;
+    t.nodecnt = a;  // last: a non-null nodecnt means the table is complete
   }
   *out = &t;
   return RS_OK;
@@ -202,6 +140,42 @@ EFLayout ef_layout(uint64_t N, uint64_t U, uint64_t at) {
   return e;
 }
 
+// Hands out aligned slices of one device region; `failed` records a slice
+// that did not fit.
+struct Carver {
+  char* base;
+  size_t cap, used = 0;
+  bool failed = false;
+  template <typename T>
+  T* take(uint64_t count) {
+    size_t bytes = (size_t)(count ? count : 1) * sizeof(T);
+    used = (used + kAlign - 1) / kAlign * kAlign;
+    if (used + bytes > cap) {
+      failed = true;
+      return nullptr;
+    }
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+hipError_t h2d(Context& c, void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.s);
+  return e == hipSuccess ? hipStreamSynchronize(c.s) : e;
+}
+
+hipError_t d2h(Context& c, void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.s);
+  return e == hipSuccess ? hipStreamSynchronize(c.s) : e;
+}
+
+// Order the context after the work already queued on the legacy default stream.
+hipError_t after_default_stream(Context& c) {
+  hipError_t e = hipEventRecord(c.upstream, 0);
+  return e == hipSuccess ? hipStreamWaitEvent(c.s, c.upstream, 0) : e;
+}
+
 }  // namespace
 
 struct rs_mphf {
@@ -218,22 +192,145 @@ struct rs_mphf {
   std::vector<uint64_t> keep_vals, keep_base;
 };
 
-namespace {
+namespace rs {
 
-void release(rs_mphf* f) {
+hipError_t ensure(Buffer& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return hipSuccess;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  size_t want = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.cap = want;
+  return hipSuccess;
+}
+
+int device_get(Device** out) {
+  int id = 0;
+  HIPCHECK(hipGetDevice(&id));
+  if (id < 0 || id >= 64) return RS_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_devices_mu);
+  Device& d = g_dev[id];
+  if (!d.ready) {
+    d.id = id;
+    HIPCHECK(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, id));
+    if (hipDeviceGetAttribute(&d.lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, id) !=
+            hipSuccess ||
+        d.lds_per_block <= 0)
+      d.lds_per_block = 65536;
+    if (hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, id) != hipSuccess ||
+        d.wall_khz <= 0)
+      d.wall_khz = 100000;
+    uint64_t h[kMaxDepth], st = 0;
+    for (uint32_t i = 0; i < kMaxDepth; ++i) h[i] = splitmix_next(st);
+    HIPCHECK(hipMalloc(&d.start, sizeof h));
+    HIPCHECK(hipMemcpy(d.start, h, sizeof h, hipMemcpyHostToDevice));
+    d.ready = true;
+  }
+  *out = &d;
+  return RS_OK;
+}
+
+int context_init(Context& c, Device* d) {
+  c.dev = d;
+  HIPCHECK(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking));
+  for (int i = 0; i < 6; ++i) HIPCHECK(hipEventCreate(&c.ev[i]));
+  HIPCHECK(hipEventCreateWithFlags(&c.upstream, hipEventDisableTiming));
+  return RS_OK;
+}
+
+void context_destroy(Context& c) {
+  if (c.s) (void)hipStreamSynchronize(c.s);
+  Buffer* bs[] = {&c.arena, &c.qkeys, &c.qout, &c.sc_counts, &c.sc_prefix, &c.sc_tmp};
+  for (Buffer* b : bs) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->cap = 0;
+  }
+  for (hipEvent_t& e : c.ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  if (c.upstream) (void)hipEventDestroy(c.upstream);
+  c.upstream = nullptr;
+  if (c.s) (void)hipStreamDestroy(c.s);
+  c.s = nullptr;
+}
+
+Context* default_context(int* rc) {
+  Device* d = nullptr;
+  *rc = device_get(&d);
+  if (*rc) return nullptr;
+  Context& c = g_default[d->id];
+  std::lock_guard<std::mutex> lock(g_devices_mu);
+  if (!c.dev) {
+    *rc = context_init(c, d);
+    if (*rc) return nullptr;
+  }
+  return &c;
+}
+
+bool job_args_ok(const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b, uint32_t flags) {
+  return l >= 2 && l <= kMaxLeaf && b >= 1 && b <= RS_MAX_BUCKET_SIZE && n < (1ull << 40) &&
+         (!n || keys) &&
+         !(flags & ~(uint32_t)(RS_FLAG_ROTATION | RS_FLAG_KEYS_ON_DEVICE | RS_FLAG_KEEP_VALUES));
+}
+
+void mphf_release(rs_mphf* f) {
   if (!f) return;
   if (f->d_words) (void)hipFree(f->d_words);
   if (f->d_samples) (void)hipFree(f->d_samples);
   delete f;
 }
 
+uint32_t max_workers(const Device& d) {
+  // occupancy of the search kernel with a small stage: the most workers any launch uses
+  int per_cu = 0;
+  if (search_occupancy(64 * sizeof(uint64_t), &per_cu) != hipSuccess || per_cu < 1) per_cu = 8;
+  return (uint32_t)per_cu * (uint32_t)d.cus;
+}
+
+size_t batch_footprint(const std::vector<JobPlan>& jobs, uint32_t workers_max) {
+  uint64_t n = 0, nb = 0, noff = 0, nhost = 0, max_nb = 1;
+  for (const JobPlan& j : jobs) {
+    if (j.status) continue;
+    const uint64_t jb = j.n ? (j.n + j.b - 1) / j.b : 1;
+    n += j.n;
+    nb += jb;
+    noff += jb + 1;
+    if (!(j.flags & RS_FLAG_KEYS_ON_DEVICE)) nhost += j.n;
+    max_nb = jb > max_nb ? jb : max_nb;
+  }
+  const uint64_t nodes = n + 1;  // stored nodes never exceed keys
+  size_t bytes = 0;
+  bytes += (nhost + 2 * n) * sizeof(Key);
+  bytes += nb * (2 * sizeof(uint32_t) + 2 * sizeof(uint64_t));
+  bytes += noff * 3 * sizeof(uint64_t);
+  bytes += scan_tmp_words(max_nb + 1) * sizeof(uint64_t);
+  bytes += nodes * (sizeof(uint64_t) + sizeof(uint32_t) + sizeof(Task) + sizeof(TaskState) +
+                    sizeof(uint32_t));
+  bytes += sizeof(Control) + jobs.size() * (sizeof(JobInfo) + sizeof(JobDev));
+  bytes += (size_t)workers_max * sizeof(int32_t);
+  bytes += 24 * kAlign;
+  return bytes;
+}
+
+}  // namespace rs
+
+namespace {
+
 // Device copy of the serialised words plus select samples of both upper
 // vectors; checks that each upper vector holds exactly N ones.
-int attach_device(Device& d, rs_mphf* f, bool words_on_device) {
+int attach_device(Context& c, rs_mphf* f, bool words_on_device) {
   const uint64_t nw = f->words.size();
   if (!words_on_device) {
     HIPCHECK(hipMalloc(&f->d_words, nw * sizeof(uint64_t)));
-    HIPCHECK(hipMemcpy(f->d_words, f->words.data(), nw * sizeof(uint64_t), hipMemcpyHostToDevice));
+    HIPCHECK(h2d(c, f->d_words, f->words.data(), nw * sizeof(uint64_t)));
   }
   f->ns_c = (f->efc.N + 255) / 256;
   f->ns_p = (f->efp.N + 255) / 256;
@@ -244,256 +341,49 @@ int attach_device(Device& d, rs_mphf* f, bool words_on_device) {
   for (int i = 0; i < 2; ++i) {
     const EFLayout& e = *efs[i];
     const uint64_t* upper = f->d_words + e.at + kEfHeaderWords + e.lw;
-    HIPCHECK(ensure(d.sc_counts, (e.uw + 1) * sizeof(uint64_t)));
-    HIPCHECK(ensure(d.sc_prefix, (e.uw + 1) * sizeof(uint64_t)));
-    HIPCHECK(ensure(d.tmp, scan_tmp_words(e.uw + 1) * sizeof(uint64_t)));
-    HIPCHECK(select_samples(upper, e.uw, as<uint64_t>(d.sc_counts), as<uint64_t>(d.sc_prefix),
-                            as<uint64_t>(d.tmp), samp[i], nsamp[i], 0));
+    HIPCHECK(ensure(c.sc_counts, (e.uw + 1) * sizeof(uint64_t)));
+    HIPCHECK(ensure(c.sc_prefix, (e.uw + 1) * sizeof(uint64_t)));
+    HIPCHECK(ensure(c.sc_tmp, scan_tmp_words(e.uw + 1) * sizeof(uint64_t)));
+    uint64_t* prefix = static_cast<uint64_t*>(c.sc_prefix.p);
+    HIPCHECK(select_samples(upper, e.uw, static_cast<uint64_t*>(c.sc_counts.p), prefix,
+                            static_cast<uint64_t*>(c.sc_tmp.p), samp[i], nsamp[i], c.s));
     uint64_t ones = 0;
-    HIPCHECK(hipMemcpy(&ones, as<uint64_t>(d.sc_prefix) + e.uw, sizeof ones, hipMemcpyDeviceToHost));
+    if (e.uw) HIPCHECK(d2h(c, &ones, prefix + e.uw, sizeof ones));
     if (ones != e.N) return RS_ERR_CORRUPT;
   }
   return RS_OK;
 }
 
-// One job of a build: its inputs, its slices of the shared device arrays, and
-// its outcome.
-struct JobPlan {
-  const Key* keys = nullptr;  // caller's keys (host or device, per flags)
-  uint64_t n = 0;
-  uint32_t l = 0, b = 0, flags = 0;
-  uint64_t nb = 0;
-  uint64_t key_base = 0;     // first key in the work arrays
-  uint64_t bucket_base = 0;  // first bucket in per-bucket arrays of nb entries
-  uint64_t off_base = 0;     // first entry in per-bucket arrays of nb + 1 entries
-  uint64_t host_base = 0;    // first key in the staging copy of host keys
-  uint64_t node_off = 0, total = 0;
-  uint32_t maxm = 0;
-  int status = RS_OK;
-  Tables* T = nullptr;
-  rs_mphf* out = nullptr;
+// Device pointers of one build, carved from its region.
+struct Arrays {
+  Key *keys_in, *k0, *k1;
+  uint32_t *cnt, *fill;
+  uint64_t *nodes, *len, *off, *node_base, *pos, *tmp;
+  uint64_t* vals;
+  uint32_t* msz;
+  Task* tasks;
+  TaskState* states;
+  uint32_t *ready, *active_u32;
+  Control* ctl;
+  JobInfo* jinfo;
+  JobDev* jobs;
 };
 
-int encode_job(Device& d, JobPlan& jp, const JobInfo& info, double ms_sort, double ms_search,
-               uint32_t workers, hipStream_t s);
-
-// Build every job whose status is RS_OK on entry; on return each job has its
-// status and, on success, its structure.  One search launch serves all jobs.
-int build_jobs(Device& d, std::vector<JobPlan>& jobs) {
-  const hipStream_t s = 0;
-  const uint32_t nj = (uint32_t)jobs.size();
-  uint64_t nkeys = 0, nbk = 0, noff = 0, nhost = 0;
-  for (JobPlan& j : jobs) {
-    j.nb = j.n ? (j.n + j.b - 1) / j.b : 1;
-    j.key_base = nkeys;
-    j.bucket_base = nbk;
-    j.off_base = noff;
-    j.host_base = nhost;
-    nkeys += j.n;
-    nbk += j.nb;
-    noff += j.nb + 1;
-    if (!(j.flags & RS_FLAG_KEYS_ON_DEVICE)) nhost += j.n;
-    int rc = tables_for(d, j.l, &j.T);
-    if (rc) return rc;
-  }
-  uint64_t max_nb = 1;
-  for (JobPlan& j : jobs) max_nb = j.nb > max_nb ? j.nb : max_nb;
-  HIPCHECK(hipEventRecord(d.ev[0], s));
-  if (nhost) HIPCHECK(ensure(d.keys_in, nhost * sizeof(Key)));
-  HIPCHECK(ensure(d.k0, nkeys * sizeof(Key)));
-  HIPCHECK(ensure(d.k1, nkeys * sizeof(Key)));
-  HIPCHECK(ensure(d.cnt, nbk * sizeof(uint32_t)));
-  HIPCHECK(ensure(d.fill, nbk * sizeof(uint32_t)));
-  HIPCHECK(ensure(d.nodes, nbk * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.len, nbk * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.off, noff * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.node_base, noff * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.pos, noff * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.tmp, scan_tmp_words(max_nb + 1) * sizeof(uint64_t)));
-  HIPCHECK(ensure(d.ctl, sizeof(Control)));
-  HIPCHECK(ensure(d.jinfo, nj * sizeof(JobInfo)));
-  HIPCHECK(ensure(d.jobs, nj * sizeof(JobDev)));
-  Control* ctl = as<Control>(d.ctl);
-  JobInfo* jinfo = as<JobInfo>(d.jinfo);
-  for (JobPlan& j : jobs)
-    if (!(j.flags & RS_FLAG_KEYS_ON_DEVICE) && j.n)
-      HIPCHECK(hipMemcpy(as<Key>(d.keys_in) + j.host_base, j.keys, j.n * sizeof(Key),
-                         hipMemcpyHostToDevice));
-  HIPCHECK(hipEventRecord(d.ev[1], s));
-
-  // 1. buckets: sizes, borders, scatter, duplicate check, node counts
-  HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(ctl), sizeof(Control) / 8, 0, s));
-  HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(jinfo), nj * sizeof(JobInfo) / 8, 0, s));
-  HIPCHECK(fill_u32(as<uint32_t>(d.cnt), nbk, 0, s));
-  HIPCHECK(fill_u32(as<uint32_t>(d.fill), nbk, 0, s));
-  for (uint32_t i = 0; i < nj; ++i) {
-    JobPlan& j = jobs[i];
-    const Key* kin =
-        (j.flags & RS_FLAG_KEYS_ON_DEVICE) ? j.keys : as<Key>(d.keys_in) + j.host_base;
-    uint32_t* cnt = as<uint32_t>(d.cnt) + j.bucket_base;
-    uint64_t* off = as<uint64_t>(d.off) + j.off_base;
-    HIPCHECK(bucket_histogram(kin, j.n, j.nb, cnt, &jinfo[i].maxm, s));
-    HIPCHECK(scan_excl_u32(cnt, j.nb, off, as<uint64_t>(d.tmp), s));
-    HIPCHECK(bucket_scatter(kin, j.n, j.nb, off, as<uint32_t>(d.fill) + j.bucket_base,
-                            as<Key>(d.k0) + j.key_base, s));
-  }
-  std::vector<JobInfo> hinfo(nj);
-  HIPCHECK(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(JobInfo), hipMemcpyDeviceToHost));
-  for (uint32_t i = 0; i < nj; ++i) {
-    JobPlan& j = jobs[i];
-    j.maxm = hinfo[i].maxm;
-    uint32_t p2 = 1;
-    while (p2 < j.maxm) p2 <<= 1;
-    // LDS of the duplicate check (next power of two) and of the search stage
-    if (j.maxm > kMaxBucketKeys || (uint64_t)p2 * 8 + 1024 > (uint64_t)d.lds_per_block)
-      j.status = RS_ERR_UNSUPPORTED;
-    if (j.status) continue;
-    const uint64_t* off = as<uint64_t>(d.off) + j.off_base;
-    HIPCHECK(duplicate_check(as<Key>(d.k0) + j.key_base, off, j.nb, j.maxm, &jinfo[i].error, s));
-    HIPCHECK(node_counts(as<uint32_t>(d.cnt) + j.bucket_base, j.nb, j.T->nodecnt,
-                         as<uint64_t>(d.nodes) + j.bucket_base, s));
-    HIPCHECK(scan_excl_u64(as<uint64_t>(d.nodes) + j.bucket_base, j.nb,
-                           as<uint64_t>(d.node_base) + j.off_base, as<uint64_t>(d.tmp), s));
-  }
-  HIPCHECK(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(JobInfo), hipMemcpyDeviceToHost));
-  uint64_t total = 0;
-  uint32_t maxm = 0;
-  for (uint32_t i = 0; i < nj; ++i) {
-    JobPlan& j = jobs[i];
-    if (j.status) continue;
-    if (hinfo[i].error) {
-      j.status = -(int)hinfo[i].error;
-      continue;
-    }
-    HIPCHECK(hipMemcpy(&j.total, as<uint64_t>(d.node_base) + j.off_base + j.nb, sizeof(uint64_t),
-                       hipMemcpyDeviceToHost));
-    j.node_off = total;
-    total += j.total;
-    maxm = j.maxm > maxm ? j.maxm : maxm;
-  }
-  if (total >= (1ull << 31)) return RS_ERR_UNSUPPORTED;
-  HIPCHECK(hipEventRecord(d.ev[2], s));
-
-  // 2. seed search over all nodes of all jobs, one persistent launch
-  uint32_t workers = 0;
-  if (total) {
-    HIPCHECK(ensure(d.vals, total * sizeof(uint64_t)));
-    HIPCHECK(ensure(d.msz, total * sizeof(uint32_t)));
-    HIPCHECK(ensure(d.tasks, total * sizeof(Task)));
-    HIPCHECK(ensure(d.states, total * sizeof(TaskState)));
-    HIPCHECK(ensure(d.ready_f, total * sizeof(uint32_t)));
-    const uint32_t lds = (maxm < 64 ? 64 : maxm) * sizeof(uint64_t);
-    int per_cu = 0;
-    HIPCHECK(search_occupancy(lds, &per_cu));
-    if (per_cu < 1) per_cu = 1;
-    workers = (uint32_t)per_cu * (uint32_t)d.cus;
-    if (const char* ew = getenv("RS_WORKERS")) {
-      const int w = atoi(ew);
-      if (w > 0 && (uint32_t)w < workers) workers = (uint32_t)w;
-    }
-    HIPCHECK(ensure(d.active, workers * sizeof(int32_t)));
-    HIPCHECK(init_states(as<TaskState>(d.states), total, s));
-    HIPCHECK(fill_u32(as<uint32_t>(d.ready_f), total, 0, s));
-    HIPCHECK(fill_u32(as<uint32_t>(d.active), workers, 0xFFFFFFFFu, s));
-    HIPCHECK(hipMemcpy(&ctl->total, &total, sizeof(uint64_t), hipMemcpyHostToDevice));
-    std::vector<JobDev> jd(nj);
-    for (uint32_t i = 0; i < nj; ++i) {
-      JobPlan& j = jobs[i];
-      JobDev& g = jd[i];
-      memset(&g, 0, sizeof g);
-      g.keys[0] = as<Key>(d.k0) + j.key_base;
-      g.keys[1] = as<Key>(d.k1) + j.key_base;
-      g.info = jinfo + i;
-      g.vals = as<uint64_t>(d.vals) + j.node_off;
-      g.msz = as<uint32_t>(d.msz) + j.node_off;
-      g.nodecnt = j.T->nodecnt;
-      g.tau = j.T->tau;
-      const Shape sh = make_shape(j.l);
-      g.l = sh.l;
-      g.la = sh.la;
-      g.ua = sh.ua;
-      g.rotation = (j.flags & RS_FLAG_ROTATION) ? 1u : 0u;
-    }
-    HIPCHECK(hipMemcpy(d.jobs.p, jd.data(), nj * sizeof(JobDev), hipMemcpyHostToDevice));
-    for (uint32_t i = 0; i < nj; ++i) {
-      JobPlan& j = jobs[i];
-      if (j.status || !j.total) continue;
-      HIPCHECK(queue_roots(as<uint32_t>(d.cnt) + j.bucket_base, as<uint64_t>(d.off) + j.off_base,
-                           as<uint64_t>(d.node_base) + j.off_base, j.nb, i, 0, 0, as<Task>(d.tasks),
-                           as<uint32_t>(d.ready_f), ctl, s));
-    }
-    SearchParams P;
-    memset(&P, 0, sizeof P);
-    P.jobs = as<JobDev>(d.jobs);
-    P.tasks = as<Task>(d.tasks);
-    P.states = as<TaskState>(d.states);
-    P.ready = as<uint32_t>(d.ready_f);
-    P.active = as<int32_t>(d.active);
-    P.ctl = ctl;
-    P.start = d.start;
-    P.workers = workers;
-    P.stage_cap = maxm;
-    // rounds of 256 attempts per claimed chunk of a split search (a schedule
-    // setting: the result does not depend on it)
-    const char* e2 = getenv("RS_ROUNDS_SPLIT");
-    P.rounds_split = e2 ? (uint32_t)atoi(e2) : 16u;
-    if (P.rounds_split < 1) P.rounds_split = 1;
-    P.cap_shift = 10;
-    P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
-    HIPCHECK(hipEventRecord(d.ev[3], s));
-    HIPCHECK(launch_search(P, workers, lds, s));
-  } else {
-    HIPCHECK(hipEventRecord(d.ev[3], s));
-  }
-  HIPCHECK(hipEventRecord(d.ev[4], s));
-  Control h_ctl;
-  HIPCHECK(hipMemcpy(&h_ctl, ctl, sizeof h_ctl, hipMemcpyDeviceToHost));
-  if (h_ctl.error && getenv("RS_DEBUG")) {
-    fprintf(stderr,
-            "[rs debug] error %u: node %llu slot %llu m %u depth %u key_off %llu np %016llx "
-            "best %llu chunk %llu finished %llu/%llu head %llu tail %llu\n",
-            h_ctl.error, (unsigned long long)h_ctl.dbg_node, (unsigned long long)h_ctl.dbg_slot,
-            h_ctl.dbg_m, h_ctl.dbg_depth, (unsigned long long)h_ctl.dbg_key_off,
-            (unsigned long long)h_ctl.dbg_np, (unsigned long long)h_ctl.dbg_best,
-            (unsigned long long)h_ctl.dbg_chunk, (unsigned long long)h_ctl.finished,
-            (unsigned long long)total, (unsigned long long)h_ctl.head,
-            (unsigned long long)h_ctl.tail);
-  }
-  int search_rc = RS_OK;
-  if (h_ctl.error) search_rc = -(int)h_ctl.error;
-  else if (h_ctl.finished != total) search_rc = RS_ERR_DEVICE;
-  HIPCHECK(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(JobInfo), hipMemcpyDeviceToHost));
-  float ms_sort = 0, ms_search = 0;
-  (void)hipEventElapsedTime(&ms_sort, d.ev[1], d.ev[2]);
-  (void)hipEventElapsedTime(&ms_search, d.ev[3], d.ev[4]);
-
-  // 3. encode every job that succeeded
-  for (uint32_t i = 0; i < nj; ++i) {
-    JobPlan& j = jobs[i];
-    if (j.status) continue;
-    if (search_rc) {
-      j.status = search_rc;
-      continue;
-    }
-    j.status = encode_job(d, j, hinfo[i], ms_sort, ms_search, workers, s);
-  }
-  return RS_OK;
-}
-
-int encode_job(Device& d, JobPlan& jp, const JobInfo& info, double ms_sort, double ms_search,
-               uint32_t workers, hipStream_t s) {
+int encode_job(Context& c, const Arrays& A, JobPlan& jp, const JobInfo& info, double ms_sort,
+               double ms_search, uint32_t workers) {
+  const hipStream_t s = c.s;
   const uint64_t nb = jp.nb;
-  const uint64_t* node_base = as<uint64_t>(d.node_base) + jp.off_base;
-  const uint64_t* vals = as<uint64_t>(d.vals) + jp.node_off;
-  const uint32_t* msz = as<uint32_t>(d.msz) + jp.node_off;
-  uint64_t* len = as<uint64_t>(d.len) + jp.bucket_base;
-  uint64_t* pos = as<uint64_t>(d.pos) + jp.off_base;
-  HIPCHECK(hipEventRecord(d.ev[4], s));
+  const uint64_t* node_base = A.node_base + jp.off_base;
+  const uint64_t* vals = A.vals + jp.node_off;
+  const uint32_t* msz = A.msz + jp.node_off;
+  uint64_t* len = A.len + jp.bucket_base;
+  uint64_t* pos = A.pos + jp.off_base;
+  HIPCHECK(hipEventRecord(c.ev[4], s));
   if (jp.total == 0) HIPCHECK(fill_u64(len, nb, 0, s));
   else HIPCHECK(gr_lengths(node_base, nb, vals, msz, jp.T->tau, len, s));
-  HIPCHECK(scan_excl_u64(len, nb, pos, as<uint64_t>(d.tmp), s));
+  HIPCHECK(scan_excl_u64(len, nb, pos, A.tmp, s));
   uint64_t gr_bits = 0;
-  HIPCHECK(hipMemcpy(&gr_bits, pos + nb, sizeof gr_bits, hipMemcpyDeviceToHost));
+  HIPCHECK(d2h(c, &gr_bits, pos + nb, sizeof gr_bits));
 
   rs_mphf* f = new (std::nothrow) rs_mphf();
   if (!f) return RS_ERR_OOM;
@@ -502,7 +392,7 @@ int encode_job(Device& d, JobPlan& jp, const JobInfo& info, double ms_sort, doub
   f->l = jp.l;
   f->b = jp.b;
   f->rotation = (jp.flags & RS_FLAG_ROTATION) ? 1u : 0u;
-  f->device = d.id;
+  f->device = c.dev->id;
   f->efc = ef_layout(nb + 1, jp.n, kHeaderWords);
   f->efp = ef_layout(nb + 1, gr_bits, f->efc.at + f->efc.words());
   f->gr_at = f->efp.at + f->efp.words();
@@ -510,50 +400,59 @@ int encode_job(Device& d, JobPlan& jp, const JobInfo& info, double ms_sort, doub
   f->gr_words = (gr_bits + 63) / 64;
   const uint64_t nw = f->gr_at + 2 + f->gr_words;
   auto fail = [&](int code) {
-    release(f);
+    mphf_release(f);
     return code;
   };
   if (hipMalloc(&f->d_words, nw * sizeof(uint64_t)) != hipSuccess) {
     f->d_words = nullptr;
     return fail(RS_ERR_OOM);
   }
-  if (fill_u64(f->d_words, nw, 0, s) != hipSuccess) return fail(RS_ERR_DEVICE);
+  // header words, staged in the structure's host copy (alive until the copies end)
+  f->words.assign(nw, 0);
   const uint64_t hdr[kHeaderWords] = {kMagic, kVersion | ((uint64_t)f->rotation << 32), jp.n,
                                       (uint64_t)jp.l | ((uint64_t)jp.b << 32), nb};
-  if (hipMemcpy(f->d_words, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess)
-    return fail(RS_ERR_DEVICE);
+  memcpy(f->words.data(), hdr, sizeof hdr);
   const EFLayout* efs[2] = {&f->efc, &f->efp};
   for (int i = 0; i < 2; ++i) {
     const EFLayout& e = *efs[i];
     const uint64_t eh[6] = {e.N, e.U, e.L, e.lw, e.ub, e.uw};
-    if (hipMemcpy(f->d_words + e.at, eh, sizeof eh, hipMemcpyHostToDevice) != hipSuccess)
+    memcpy(f->words.data() + e.at, eh, sizeof eh);
+  }
+  f->words[f->gr_at] = gr_bits;
+  f->words[f->gr_at + 1] = f->gr_words;
+  // zero the structure, place the headers; kernels write the rest
+  if (fill_u64(f->d_words, nw, 0, s) != hipSuccess ||
+      hipMemcpyAsync(f->d_words, f->words.data(), kHeaderWords * 8, hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return fail(RS_ERR_DEVICE);
+  for (int i = 0; i < 2; ++i) {
+    const EFLayout& e = *efs[i];
+    if (hipMemcpyAsync(f->d_words + e.at, f->words.data() + e.at, kEfHeaderWords * 8,
+                       hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(RS_ERR_DEVICE);
   }
-  const uint64_t gh[2] = {gr_bits, f->gr_words};
-  if (hipMemcpy(f->d_words + f->gr_at, gh, sizeof gh, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpyAsync(f->d_words + f->gr_at, f->words.data() + f->gr_at, 16, hipMemcpyHostToDevice,
+                     s) != hipSuccess)
     return fail(RS_ERR_DEVICE);
   uint64_t* gr = f->d_words + f->gr_at + 2;
   if (jp.total && gr_write(node_base, nb, vals, msz, jp.T->tau, pos, gr, s) != hipSuccess)
     return fail(RS_ERR_DEVICE);
-  const uint64_t* xs[2] = {as<uint64_t>(d.off) + jp.off_base, pos};
+  const uint64_t* xs[2] = {A.off + jp.off_base, pos};
   for (int i = 0; i < 2; ++i) {
     const EFLayout& e = *efs[i];
     if (ef_write(xs[i], e.N, (uint32_t)e.L, f->d_words + e.at + kEfHeaderWords,
                  f->d_words + e.at + kEfHeaderWords + e.lw, s) != hipSuccess)
       return fail(RS_ERR_DEVICE);
   }
-  if (hipEventRecord(d.ev[5], s) != hipSuccess) return fail(RS_ERR_DEVICE);
-  f->words.resize(nw);
-  if (hipMemcpy(f->words.data(), f->d_words, nw * 8, hipMemcpyDeviceToHost) != hipSuccess)
-    return fail(RS_ERR_DEVICE);
-  int rc = attach_device(d, f, true);
+  if (hipEventRecord(c.ev[5], s) != hipSuccess) return fail(RS_ERR_DEVICE);
+  if (d2h(c, f->words.data(), f->d_words, nw * 8) != hipSuccess) return fail(RS_ERR_DEVICE);
+  int rc = attach_device(c, f, true);
   if (rc) return fail(rc);
   if (jp.flags & RS_FLAG_KEEP_VALUES) {
     f->keep_vals.resize(jp.total);
     f->keep_base.resize(nb + 1);
-    if ((jp.total && hipMemcpy(f->keep_vals.data(), vals, jp.total * 8, hipMemcpyDeviceToHost) !=
-                         hipSuccess) ||
-        hipMemcpy(f->keep_base.data(), node_base, (nb + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    if ((jp.total && d2h(c, f->keep_vals.data(), vals, jp.total * 8) != hipSuccess) ||
+        d2h(c, f->keep_base.data(), node_base, (nb + 1) * 8) != hipSuccess)
       return fail(RS_ERR_DEVICE);
   }
   rs_stats& st = f->stats;
@@ -572,27 +471,245 @@ int encode_job(Device& d, JobPlan& jp, const JobInfo& info, double ms_sort, doub
   float ms = 0;
   st.ms_sort = ms_sort;
   st.ms_search = ms_search;
-  (void)hipEventElapsedTime(&ms, d.ev[4], d.ev[5]);
+  (void)hipEventElapsedTime(&ms, c.ev[4], c.ev[5]);
   st.ms_encode = ms;
-  (void)hipEventElapsedTime(&ms, d.ev[0], d.ev[5]);
+  (void)hipEventElapsedTime(&ms, c.ev[0], c.ev[5]);
   st.ms_total = ms;
   jp.out = f;
   return RS_OK;
 }
 
-int build_locked(Device& d, const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b,
-                 uint32_t flags, rs_mphf** out) {
-  std::vector<JobPlan> jobs(1);
-  jobs[0].keys = reinterpret_cast<const Key*>(keys);
-  jobs[0].n = n;
-  jobs[0].l = l;
-  jobs[0].b = b;
-  jobs[0].flags = flags;
-  int rc = build_jobs(d, jobs);
-  if (rc) return rc;
-  if (jobs[0].status) return jobs[0].status;
-  *out = jobs[0].out;
+}  // namespace
+
+namespace rs {
+
+int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t region_bytes,
+               uint32_t workers_cap) {
+  Device& d = *c.dev;
+  const hipStream_t s = c.s;
+  const uint32_t nj = (uint32_t)jobs.size();
+  uint64_t nkeys = 0, nbk = 0, noff = 0, nhost = 0, max_nb = 1;
+  for (JobPlan& j : jobs) {
+    if (j.status) continue;
+    j.nb = j.n ? (j.n + j.b - 1) / j.b : 1;
+    j.key_base = nkeys;
+    j.bucket_base = nbk;
+    j.off_base = noff;
+    j.host_base = nhost;
+    nkeys += j.n;
+    nbk += j.nb;
+    noff += j.nb + 1;
+    if (!(j.flags & RS_FLAG_KEYS_ON_DEVICE)) nhost += j.n;
+    max_nb = j.nb > max_nb ? j.nb : max_nb;
+    int rc = tables_for(d, j.l, &j.T);
+    if (rc) return rc;
+  }
+  const uint32_t wmax = max_workers(d);
+  uint32_t workers = workers_cap && workers_cap < wmax ? workers_cap : wmax;
+  if (const char* ew = getenv("RS_WORKERS")) {
+    const int w = atoi(ew);
+    if (w > 0 && (uint32_t)w < workers) workers = (uint32_t)w;
+  }
+  if (batch_footprint(jobs, wmax) > region_bytes) return RS_ERR_OOM;
+  Carver cv{static_cast<char*>(region), region_bytes};
+  Arrays A;
+  A.keys_in = cv.take<Key>(nhost);
+  A.k0 = cv.take<Key>(nkeys);
+  A.k1 = cv.take<Key>(nkeys);
+  A.cnt = cv.take<uint32_t>(nbk);
+  A.fill = cv.take<uint32_t>(nbk);
+  A.nodes = cv.take<uint64_t>(nbk);
+  A.len = cv.take<uint64_t>(nbk);
+  A.off = cv.take<uint64_t>(noff);
+  A.node_base = cv.take<uint64_t>(noff);
+  A.pos = cv.take<uint64_t>(noff);
+  A.tmp = cv.take<uint64_t>(scan_tmp_words(max_nb + 1));
+  A.ctl = cv.take<Control>(1);
+  A.jinfo = cv.take<JobInfo>(nj);
+  A.jobs = cv.take<JobDev>(nj);
+  A.active_u32 = cv.take<uint32_t>(wmax);
+  const uint64_t node_cap = nkeys + 1;
+  A.vals = cv.take<uint64_t>(node_cap);
+  A.msz = cv.take<uint32_t>(node_cap);
+  A.tasks = cv.take<Task>(node_cap);
+  A.states = cv.take<TaskState>(node_cap);
+  A.ready = cv.take<uint32_t>(node_cap);
+  if (cv.failed) return RS_ERR_OOM;
+
+  HIPCHECK(hipEventRecord(c.ev[0], s));
+  HIPCHECK(after_default_stream(c));
+  for (JobPlan& j : jobs)
+    if (!j.status && !(j.flags & RS_FLAG_KEYS_ON_DEVICE) && j.n)
+      HIPCHECK(hipMemcpyAsync(A.keys_in + j.host_base, j.keys, j.n * sizeof(Key),
+                              hipMemcpyHostToDevice, s));
+  HIPCHECK(hipEventRecord(c.ev[1], s));
+
+  // 1. buckets: sizes, borders, scatter, duplicate check, node counts
+  HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(A.ctl), sizeof(Control) / 8, 0, s));
+  HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(A.jinfo), nj * sizeof(JobInfo) / 8, 0, s));
+  HIPCHECK(fill_u32(A.cnt, nbk, 0, s));
+  HIPCHECK(fill_u32(A.fill, nbk, 0, s));
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    if (j.status) continue;
+    const Key* kin = (j.flags & RS_FLAG_KEYS_ON_DEVICE) ? j.keys : A.keys_in + j.host_base;
+    uint32_t* cnt = A.cnt + j.bucket_base;
+    uint64_t* off = A.off + j.off_base;
+    HIPCHECK(bucket_histogram(kin, j.n, j.nb, cnt, &A.jinfo[i].maxm, s));
+    HIPCHECK(scan_excl_u32(cnt, j.nb, off, A.tmp, s));
+    HIPCHECK(bucket_scatter(kin, j.n, j.nb, off, A.fill + j.bucket_base, A.k0 + j.key_base, s));
+  }
+  std::vector<JobInfo> hinfo(nj);
+  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    if (j.status) continue;
+    j.maxm = hinfo[i].maxm;
+    uint32_t p2 = 1;
+    while (p2 < j.maxm) p2 <<= 1;
+    // LDS of the duplicate check (next power of two) and of the search stage
+    if (j.maxm > kMaxBucketKeys || (uint64_t)p2 * 8 + 1024 > (uint64_t)d.lds_per_block) {
+      j.status = RS_ERR_UNSUPPORTED;
+      continue;
+    }
+    HIPCHECK(duplicate_check(A.k0 + j.key_base, A.off + j.off_base, j.nb, j.maxm,
+                             &A.jinfo[i].error, s));
+    HIPCHECK(node_counts(A.cnt + j.bucket_base, j.nb, j.T->nodecnt, A.nodes + j.bucket_base, s));
+    HIPCHECK(scan_excl_u64(A.nodes + j.bucket_base, j.nb, A.node_base + j.off_base, A.tmp, s));
+  }
+  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
+  uint64_t total = 0;
+  uint32_t maxm = 0;
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    if (j.status) continue;
+    if (hinfo[i].error) {
+      j.status = -(int)hinfo[i].error;
+      continue;
+    }
+    HIPCHECK(d2h(c, &j.total, A.node_base + j.off_base + j.nb, sizeof(uint64_t)));
+    j.node_off = total;
+    total += j.total;
+    maxm = j.maxm > maxm ? j.maxm : maxm;
+  }
+  if (total >= (1ull << 31) || total > node_cap) return RS_ERR_UNSUPPORTED;
+  HIPCHECK(hipEventRecord(c.ev[2], s));
+
+  // 2. seed search over all nodes of all jobs, one persistent launch
+  if (total) {
+    const uint32_t lds = (maxm < 64 ? 64 : maxm) * sizeof(uint64_t);
+    int per_cu = 0;
+    HIPCHECK(search_occupancy(lds, &per_cu));
+    if (per_cu < 1) per_cu = 1;
+    const uint32_t occ = (uint32_t)per_cu * (uint32_t)d.cus;
+    if (workers > occ) workers = occ;
+    HIPCHECK(init_states(A.states, total, s));
+    HIPCHECK(fill_u32(A.ready, total, 0, s));
+    HIPCHECK(fill_u32(A.active_u32, workers, 0xFFFFFFFFu, s));
+    std::vector<JobDev> jd(nj);
+    for (uint32_t i = 0; i < nj; ++i) {
+      JobPlan& j = jobs[i];
+      JobDev& g = jd[i];
+      memset(&g, 0, sizeof g);
+      if (j.status) continue;
+      g.keys[0] = A.k0 + j.key_base;
+      g.keys[1] = A.k1 + j.key_base;
+      g.info = A.jinfo + i;
+      g.vals = A.vals + j.node_off;
+      g.msz = A.msz + j.node_off;
+      g.nodecnt = j.T->nodecnt;
+      g.tau = j.T->tau;
+      const Shape sh = make_shape(j.l);
+      g.l = sh.l;
+      g.la = sh.la;
+      g.ua = sh.ua;
+      g.rotation = (j.flags & RS_FLAG_ROTATION) ? 1u : 0u;
+    }
+    HIPCHECK(h2d(c, A.jobs, jd.data(), nj * sizeof(JobDev)));
+    HIPCHECK(h2d(c, &A.ctl->total, &total, sizeof(uint64_t)));
+    for (uint32_t i = 0; i < nj; ++i) {
+      JobPlan& j = jobs[i];
+      if (j.status || !j.total) continue;
+      HIPCHECK(queue_roots(A.cnt + j.bucket_base, A.off + j.off_base, A.node_base + j.off_base,
+                           j.nb, i, 0, 0, A.tasks, A.ready, A.ctl, s));
+    }
+    SearchParams P;
+    memset(&P, 0, sizeof P);
+    P.jobs = A.jobs;
+    P.tasks = A.tasks;
+    P.states = A.states;
+    P.ready = A.ready;
+    P.active = reinterpret_cast<int32_t*>(A.active_u32);
+    P.ctl = A.ctl;
+    P.start = d.start;
+    P.workers = workers;
+    P.stage_cap = maxm;
+    // rounds of 256 attempts per claimed chunk of a split search (a schedule
+    // setting: the result does not depend on it)
+    const char* e2 = getenv("RS_ROUNDS_SPLIT");
+    P.rounds_split = e2 ? (uint32_t)atoi(e2) : 16u;
+    if (P.rounds_split < 1) P.rounds_split = 1;
+    P.cap_shift = 10;
+    P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
+    HIPCHECK(hipEventRecord(c.ev[3], s));
+    HIPCHECK(launch_search(P, workers, lds, s));
+  } else {
+    HIPCHECK(hipEventRecord(c.ev[3], s));
+  }
+  HIPCHECK(hipEventRecord(c.ev[4], s));
+  Control h_ctl;
+  HIPCHECK(d2h(c, &h_ctl, A.ctl, sizeof h_ctl));
+  if (h_ctl.error && getenv("RS_DEBUG")) {
+    fprintf(stderr,
+            "[rs debug] error %u: node %llu slot %llu m %u depth %u key_off %llu np %016llx "
+            "best %llu chunk %llu finished %llu/%llu head %llu tail %llu\n",
+            h_ctl.error, (unsigned long long)h_ctl.dbg_node, (unsigned long long)h_ctl.dbg_slot,
+            h_ctl.dbg_m, h_ctl.dbg_depth, (unsigned long long)h_ctl.dbg_key_off,
+            (unsigned long long)h_ctl.dbg_np, (unsigned long long)h_ctl.dbg_best,
+            (unsigned long long)h_ctl.dbg_chunk, (unsigned long long)h_ctl.finished,
+            (unsigned long long)total, (unsigned long long)h_ctl.head,
+            (unsigned long long)h_ctl.tail);
+  }
+  int search_rc = RS_OK;
+  if (h_ctl.error) search_rc = -(int)h_ctl.error;
+  else if (h_ctl.finished != total) search_rc = RS_ERR_DEVICE;
+  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
+  float ms_sort = 0, ms_search = 0;
+  (void)hipEventElapsedTime(&ms_sort, c.ev[1], c.ev[2]);
+  (void)hipEventElapsedTime(&ms_search, c.ev[3], c.ev[4]);
+
+  // 3. encode every job that succeeded
+  for (uint32_t i = 0; i < nj; ++i) {
+    JobPlan& j = jobs[i];
+    if (j.status) continue;
+    if (search_rc) {
+      j.status = search_rc;
+      continue;
+    }
+    j.status = encode_job(c, A, j, hinfo[i], ms_sort, ms_search, workers);
+  }
   return RS_OK;
+}
+
+}  // namespace rs
+
+namespace {
+
+// Run a batch on the default context, in its growable working region.
+int build_on_default(std::vector<JobPlan>& plan) {
+  int rc = RS_OK;
+  Context* c = default_context(&rc);
+  if (!c) return rc;
+  std::lock_guard<std::mutex> lock(c->mu);
+  const size_t need = batch_footprint(plan, max_workers(*c->dev));
+  HIPCHECK(ensure(c->arena, need));
+  rc = build_jobs(*c, plan, c->arena.p, c->arena.cap, 0);
+  if (rc) {
+    // leave the stream usable for the next call
+    (void)hipStreamSynchronize(c->s);
+    (void)hipGetLastError();
+  }
+  return rc;
 }
 
 int parse(const uint64_t* w, uint64_t nw, rs_mphf* f) {
@@ -633,28 +750,22 @@ int parse(const uint64_t* w, uint64_t nw, rs_mphf* f) {
 
 extern "C" {
 
-static bool job_args_ok(const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b, uint32_t flags) {
-  return l >= 2 && l <= kMaxLeaf && b >= 1 && b <= RS_MAX_BUCKET_SIZE && n < (1ull << 40) &&
-         (!n || keys) &&
-         !(flags & ~(uint32_t)(RS_FLAG_ROTATION | RS_FLAG_KEYS_ON_DEVICE | RS_FLAG_KEEP_VALUES));
-}
-
 int rs_build(const rs_key128* keys, uint64_t n, uint32_t leaf_size, uint32_t bucket_size,
              uint32_t flags, rs_mphf** out) {
   if (!out) return RS_ERR_INVALID_ARG;
   *out = nullptr;
   if (!job_args_ok(keys, n, leaf_size, bucket_size, flags)) return RS_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> lock(g_mu);
-  Device* d = nullptr;
-  int rc = device_init(&d);
+  std::vector<JobPlan> plan(1);
+  plan[0].keys = reinterpret_cast<const Key*>(keys);
+  plan[0].n = n;
+  plan[0].l = leaf_size;
+  plan[0].b = bucket_size;
+  plan[0].flags = flags;
+  int rc = build_on_default(plan);
   if (rc) return rc;
-  rc = build_locked(*d, keys, n, leaf_size, bucket_size, flags, out);
-  if (rc) {
-    // leave the device usable for the next call
-    (void)hipDeviceSynchronize();
-    (void)hipGetLastError();
-  }
-  return rc;
+  if (plan[0].status) return plan[0].status;
+  *out = plan[0].out;
+  return RS_OK;
 }
 
 int rs_build_batch(const rs_job* jobs, uint32_t njobs, rs_mphf** outs, int* statuses) {
@@ -678,27 +789,19 @@ int rs_build_batch(const rs_job* jobs, uint32_t njobs, rs_mphf** outs, int* stat
     plan.push_back(p);
     index.push_back(i);
   }
-  int first = RS_OK;
   if (!plan.empty()) {
-    std::lock_guard<std::mutex> lock(g_mu);
-    Device* d = nullptr;
-    int rc = device_init(&d);
-    if (!rc) rc = build_jobs(*d, plan);
-    if (rc) {
-      (void)hipDeviceSynchronize();
-      (void)hipGetLastError();
-    }
+    const int rc = build_on_default(plan);
     for (size_t k = 0; k < plan.size(); ++k) {
       if (rc) {
-        release(plan[k].out);
+        mphf_release(plan[k].out);
         plan[k].out = nullptr;
         plan[k].status = rc;
       }
       statuses[index[k]] = plan[k].status;
       outs[index[k]] = plan[k].status ? nullptr : plan[k].out;
-      if (plan[k].status && plan[k].out) release(plan[k].out);
     }
   }
+  int first = RS_OK;
   for (uint32_t i = 0; i < njobs; ++i)
     if (statuses[i] && !first) first = statuses[i];
   return first;
@@ -708,22 +811,25 @@ int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out,
   if (!f || (n && (!keys || !out)) || (flags & ~(uint32_t)RS_FLAG_KEYS_ON_DEVICE))
     return RS_ERR_INVALID_ARG;
   if (!n) return RS_OK;
-  std::lock_guard<std::mutex> lock(g_mu);
-  Device* d = nullptr;
-  int rc = device_init(&d);
-  if (rc) return rc;
+  int rc = RS_OK;
+  Context* c = default_context(&rc);
+  if (!c) return rc;
+  std::lock_guard<std::mutex> lock(c->mu);
+  Device& d = *c->dev;
   Tables* T = nullptr;
-  rc = tables_for(*d, f->l, &T);
+  rc = tables_for(d, f->l, &T);
   if (rc) return rc;
   const Key* kd = reinterpret_cast<const Key*>(keys);
   uint64_t* od = out;
   const bool on_dev = (flags & RS_FLAG_KEYS_ON_DEVICE) != 0;
-  if (!on_dev) {
-    HIPCHECK(ensure(d->qkeys, n * sizeof(Key)));
-    HIPCHECK(ensure(d->qout, n * sizeof(uint64_t)));
-    HIPCHECK(hipMemcpy(d->qkeys.p, keys, n * sizeof(Key), hipMemcpyHostToDevice));
-    kd = as<Key>(d->qkeys);
-    od = as<uint64_t>(d->qout);
+  if (on_dev) {
+    HIPCHECK(after_default_stream(*c));
+  } else {
+    HIPCHECK(ensure(c->qkeys, n * sizeof(Key)));
+    HIPCHECK(ensure(c->qout, n * sizeof(uint64_t)));
+    HIPCHECK(hipMemcpyAsync(c->qkeys.p, keys, n * sizeof(Key), hipMemcpyHostToDevice, c->s));
+    kd = static_cast<const Key*>(c->qkeys.p);
+    od = static_cast<uint64_t*>(c->qout.p);
   }
   QueryParams q;
   q.C.lower = f->d_words + f->efc.at + kEfHeaderWords;
@@ -744,10 +850,10 @@ int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out,
   q.nodecnt = T->nodecnt;
   q.fixedbits = T->fixedbits;
   q.tau = T->tau;
-  q.start = d->start;
-  HIPCHECK(launch_query(q, kd, n, od, 0));
-  if (!on_dev) HIPCHECK(hipMemcpy(out, od, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
-  else HIPCHECK(hipStreamSynchronize(0));
+  q.start = d.start;
+  HIPCHECK(launch_query(q, kd, n, od, c->s));
+  if (!on_dev) HIPCHECK(d2h(*c, out, od, n * sizeof(uint64_t)));
+  else HIPCHECK(hipStreamSynchronize(c->s));
   return RS_OK;
 }
 
@@ -768,18 +874,19 @@ int rs_deserialize(const uint8_t* bytes, uint64_t nbytes, rs_mphf** out) {
   if (nbytes) memcpy(f->words.data(), bytes, nbytes);
   int rc = parse(f->words.data(), f->words.size(), f);
   if (rc) {
-    release(f);
+    mphf_release(f);
     return rc;
   }
-  std::lock_guard<std::mutex> lock(g_mu);
-  Device* d = nullptr;
-  rc = device_init(&d);
-  if (!rc) rc = attach_device(*d, f, false);
+  Context* c = default_context(&rc);
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->mu);
+    rc = attach_device(*c, f, false);
+  }
   if (rc) {
-    release(f);
+    mphf_release(f);
     return rc;
   }
-  f->device = d->id;
+  f->device = c->dev->id;
   f->stats.n = f->n;
   f->stats.nb = f->nb;
   f->stats.gr_bits = f->gr_bits;
@@ -804,11 +911,12 @@ int rs_get_stats(const rs_mphf* f, rs_stats* st) {
   return RS_OK;
 }
 
-void rs_free(rs_mphf* f) { release(f); }
+void rs_free(rs_mphf* f) { mphf_release(f); }
 
 const char* rs_strerror(int code) {
   switch (code) {
     case RS_OK: return "ok";
+    case RS_PENDING: return "not finished yet";
     case RS_ERR_INVALID_ARG: return "invalid argument";
     case RS_ERR_DUPLICATE: return "two keys of one bucket share their hashed word";
     case RS_ERR_OOM: return "out of memory";

@@ -60,6 +60,39 @@ def fingerprints(n: int, seed: int) -> np.ndarray:
         out = np.concatenate([out[keep], extra])
 
 
+def _as_signed(x: int) -> int:
+    x &= 0xFFFFFFFFFFFFFFFF
+    return x - (1 << 64) if x >> 63 else x
+
+
+def _lsr(z, k: int):
+    """Logical right shift of int64 tensors (torch's >> is arithmetic)."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def fingerprints_torch(n: int, seed: int, device="cuda"):
+    """The keys of ``fingerprints(n, seed)`` drawn with torch on ``device``, as
+    an (n, 2) int64 tensor holding the same 64-bit words (two's complement
+    int64 arithmetic wraps exactly like uint64).  If two drawn keys share w0
+    the exact host procedure (with its redraws) is used instead."""
+    import torch
+
+    if n == 0:
+        return torch.zeros((0, 2), dtype=torch.int64, device=device)
+    idx = torch.arange(1, 2 * n + 1, dtype=torch.int64, device=device)
+    z = idx * _as_signed(int(GOLDEN)) + _as_signed(seed)
+    z = z ^ _lsr(z, 30)
+    z = z * _as_signed(int(_M1))
+    z = z ^ _lsr(z, 27)
+    z = z * _as_signed(int(_M2))
+    z = z ^ _lsr(z, 31)
+    out = z.view(n, 2)
+    w0 = torch.sort(out[:, 0])[0]
+    if n > 1 and bool((w0[1:] == w0[:-1]).any()):
+        return torch.from_numpy(fingerprints(n, seed).view(np.int64)).to(device)
+    return out
+
+
 def _unit(x: np.ndarray) -> np.ndarray:
     """Uniform doubles in [0, 1) from the top 53 bits."""
     return (x >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "librecsplit.so")
 RS_FLAG_ROTATION = 1
 RS_FLAG_KEYS_ON_DEVICE = 2
 RS_FLAG_KEEP_VALUES = 4
+RS_PENDING = 1
 
 ERRORS = {0: "RS_OK", -1: "RS_ERR_INVALID_ARG", -2: "RS_ERR_DUPLICATE", -3: "RS_ERR_OOM",
           -4: "RS_ERR_DEVICE", -5: "RS_ERR_CORRUPT", -6: "RS_ERR_SEARCH_LIMIT",
@@ -76,6 +77,8 @@ _lib.rs_serialize.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64)]
 _lib.rs_deserialize.argtypes = [_vp, _u64, ctypes.POINTER(_vp)]
 _lib.rs_debug_node_values.argtypes = [_vp, _u64, _vp, _u64, ctypes.POINTER(_u64)]
 _lib.rs_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+
+
 class Job(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("n", ctypes.c_uint64), ("leaf_size", ctypes.c_uint32),
                 ("bucket_size", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
@@ -84,12 +87,45 @@ class Job(ctypes.Structure):
 _lib.rs_build_batch.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(_vp),
                                 ctypes.POINTER(ctypes.c_int)]
 _lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
+                ("max_jobs_per_launch", ctypes.c_uint32)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("submit", ctypes.c_double), ("admit", ctypes.c_double),
+                ("done", ctypes.c_double), ("slot", ctypes.c_uint32),
+                ("batch_jobs", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "launches",
+                                                "keys_completed", "waiting", "bytes_in_use",
+                                                "peak_bytes")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib.rs_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
+_lib.rs_server_submit.argtypes = [_vp, ctypes.POINTER(Job), ctypes.POINTER(_u64)]
+_lib.rs_server_poll.argtypes = [_vp, _u64, ctypes.c_int, ctypes.POINTER(_vp),
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(RequestTimes)]
+_lib.rs_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+_lib.rs_server_destroy.argtypes = [_vp]
+_lib.rs_server_destroy.restype = None
 _lib.rs_free.argtypes = [_vp]
 _lib.rs_free.restype = None
 _lib.rs_strerror.argtypes = [ctypes.c_int]
 _lib.rs_strerror.restype = ctypes.c_char_p
 for _f in ("rs_build", "rs_build_batch", "rs_query", "rs_serialize", "rs_deserialize",
-           "rs_debug_node_values", "rs_get_stats", "rs_calibrate_valu"):
+           "rs_debug_node_values", "rs_get_stats", "rs_calibrate_valu", "rs_server_create",
+           "rs_server_submit", "rs_server_poll", "rs_server_get_stats"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -188,6 +224,66 @@ def build_batch(jobs):
     _lib.rs_build_batch(arr, len(jobs), outs, st)
     res = [MPHF(outs[i]) if outs[i] else None for i in range(len(jobs))]
     return res, [int(st[i]) for i in range(len(jobs))]
+
+
+class Server:
+    """rs_server_*: continuous batching of build requests under an HBM budget.
+
+    submit() queues a request and returns its ticket; the key array is kept
+    alive here until its result is collected with poll()/wait()."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, max_jobs_per_launch: int = 16):
+        cfg = ServerConfig(hbm_budget_bytes, max_slots, max_jobs_per_launch)
+        h = ctypes.c_void_p()
+        _check(_lib.rs_server_create(ctypes.byref(cfg), ctypes.byref(h)), "rs_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, keys, leaf_size: int, bucket_size: int, rotation: bool = True,
+               keep_values: bool = False) -> int:
+        ptr, n, flags, k = _keys_arg(keys)
+        flags |= (RS_FLAG_ROTATION if rotation else 0) | (RS_FLAG_KEEP_VALUES if keep_values else 0)
+        job = Job(ptr, n, leaf_size, bucket_size, flags)
+        t = ctypes.c_uint64()
+        _check(_lib.rs_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)),
+               "rs_server_submit")
+        self._keep[t.value] = k
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """None while pending; else (MPHF or None, status, times dict)."""
+        h, st, tm = ctypes.c_void_p(), ctypes.c_int(), RequestTimes()
+        rc = _lib.rs_server_poll(self._h, ticket, 1 if wait else 0, ctypes.byref(h),
+                                 ctypes.byref(st), ctypes.byref(tm))
+        if rc == RS_PENDING:
+            return None
+        _check(rc, "rs_server_poll")
+        self._keep.pop(ticket, None)
+        return (MPHF(h.value) if h.value else None), st.value, tm.as_dict()
+
+    def wait(self, ticket: int):
+        return self.poll(ticket, wait=True)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.rs_server_get_stats(self._h, ctypes.byref(st)), "rs_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.rs_server_destroy(h)
+            self._h = ctypes.c_void_p(0)
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()
 
 
 def deserialize(data: bytes) -> MPHF:

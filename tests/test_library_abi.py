@@ -70,3 +70,28 @@ def test_keygen_is_duplicate_free_and_deterministic():
                and j["bucket_size"] in (100, 500, 2000) for j in jobs)
     reqs = keygen.served_requests(50)
     assert all(reqs[i]["arrival"] < reqs[i + 1]["arrival"] for i in range(49))
+
+
+def test_torch_keygen_draws_the_same_keys():
+    import numpy as np
+
+    from paper_2212_09562_amd import keygen
+
+    for n, seed in ((0, 1), (1, 0), (4097, 3), (100000, (5 << 32) + 7), (33, (1 << 64) - 1)):
+        a = keygen.fingerprints(n, seed)
+        b = keygen.fingerprints_torch(n, seed, "cpu").numpy().view(np.uint64)
+        assert np.array_equal(a, b), (n, seed)
+
+
+def test_server_config_rejected_before_any_device_call():
+    import ctypes
+
+    from paper_2212_09562_amd import recsplit
+
+    lib = recsplit.library()
+    h = ctypes.c_void_p()
+    for budget, slots in ((1 << 30, 0), (1 << 30, 65), (1000, 2)):
+        cfg = recsplit.ServerConfig(budget, slots, 4)
+        assert lib.rs_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert lib.rs_server_create(None, ctypes.byref(h)) == -1
+    assert recsplit.strerror(recsplit.RS_PENDING) != "unknown error"
