@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -87,6 +88,153 @@ def cpu_baseline(keys, l, b, buckets):
             "seconds": dt, "useful_evals_per_s": (st["evals_split"] + st["evals_leaf"]) / dt}
 
 
+def _search_roofline(evals, ms_search):
+    evals_per_s = evals / (ms_search * 1e-3)
+    achieved = evals_per_s * OPS_PER_EVAL / 1e12
+    return {"hash_evals_per_s": evals_per_s, "achieved_tops": achieved,
+            "frac": achieved / (PEAK_LANE_OPS / 1e12), "ms_search": ms_search}
+
+
+def run_batched(recsplit, keygen, torch, steps, warmup):
+    """64 independent key sets (sizes log-uniform in [10^3, 10^6], l in
+    {8, 12, 16}, b in {100, 500, 2000}, seed 4), device resident: one
+    rs_build_batch call (one persistent search launch for all sets) against
+    the same sets built by 64 plain rs_build calls, one after another."""
+    jobs = keygen.batched_jobs(64, seed=4,
+                               draw=lambda n, sd: keygen.fingerprints_torch(n, sd, "cuda"))
+    total = sum(j["n"] for j in jobs)
+    batch = [{"keys": j["keys"], "leaf_size": j["leaf_size"], "bucket_size": j["bucket_size"]}
+             for j in jobs]
+    torch.cuda.synchronize()
+
+    def one_batch():
+        outs, st = recsplit.build_batch(batch)
+        if any(st):
+            raise RuntimeError(f"batch build failed: {st}")
+        return outs
+
+    def one_plain():
+        return [recsplit.build(j["keys"], j["leaf_size"], j["bucket_size"], True) for j in jobs]
+
+    for _ in range(warmup):
+        one_batch()
+        one_plain()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs = one_batch()
+    t_batch = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain = one_plain()
+    t_plain = (time.perf_counter() - t0) / steps
+    same = all(a.serialize() == b.serialize() for a, b in zip(outs, plain))
+    stats = [o.stats() for o in outs]
+    evals = sum(x["useful_evals_split"] + x["useful_evals_leaf"] for x in stats)
+    return {"workload": "64 key sets, sizes log-uniform in [1e3, 1e6], l in {8,12,16}, "
+                        "b in {100,500,2000}, rotation fitting, seed 4",
+            "keys": total, "batched_keys_per_s": total / t_batch,
+            "plain_keys_per_s": total / t_plain, "speedup_vs_plain": t_plain / t_batch,
+            "ms_batched": t_batch * 1e3, "ms_plain": t_plain * 1e3,
+            "identical_to_plain": same, "useful_hash_evals": evals,
+            "search": _search_roofline(evals, stats[0]["ms_search"])}
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(math.ceil(q / 100.0 * len(xs))) - 1)]
+
+
+def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch):
+    """Construction requests with Poisson arrivals (20 per second) and sizes
+    log-uniform in [10^4, 10^7] keys, l = 12, b = 1000, rotation fitting
+    (seed 5), keys resident in HBM.  Three runs over the same requests:
+    plain rs_build calls one after another; the server with every request
+    queued at once (its capacity); the server fed at the arrival times
+    (latency).  A single-queue server using plain launches is replayed from
+    the measured plain build times for the same arrivals."""
+    reqs = keygen.served_requests(count, seed=5)
+    keys = [keygen.fingerprints_torch(r["n"], r["seed"], "cuda") for r in reqs]
+    torch.cuda.synchronize()
+    total = sum(r["n"] for r in reqs)
+    l, b = 12, 1000
+    budget = int(budget_gib * (1 << 30))
+    recsplit.build(keys[0], l, b, True).free()  # warm-up
+    # plain launches, one request at a time
+    plain_s, plain_f = [], []
+    t0 = time.perf_counter()
+    for k in keys:
+        a = time.perf_counter()
+        plain_f.append(recsplit.build(k, l, b, True))
+        plain_s.append(time.perf_counter() - a)
+    t_plain = time.perf_counter() - t0
+    plain_digest = [hashlib.sha256(f.serialize()).digest() for f in plain_f]
+    del plain_f
+    # FIFO single-queue server with plain launches, replayed at the arrival times
+    fin, plain_lat = 0.0, []
+    for r, s in zip(reqs, plain_s):
+        fin = max(fin, r["arrival"]) + s
+        plain_lat.append(fin - r["arrival"])
+    with recsplit.Server(budget, max_slots=slots, max_jobs_per_launch=per_launch) as srv:
+        # capacity: every request queued at once
+        t0 = time.perf_counter()
+        tickets = [srv.submit(k, l, b, True) for k in keys]
+        res = [srv.wait(t) for t in tickets]
+        t_sat = time.perf_counter() - t0
+        same = all(hashlib.sha256(f.serialize()).digest() == d
+                   for (f, st, _), d in zip(res, plain_digest))
+        ok = all(st == 0 for (_, st, _) in res)
+        del res
+        sat_stats = srv.stats()
+        # arrivals at their Poisson times
+        import threading
+
+        done = [None] * len(reqs)
+
+        def collect(i, t):
+            f, st, tm = srv.wait(t)
+            done[i] = (st, tm)
+            if f is not None:
+                f.free()
+
+        threads = []
+        t_base = time.perf_counter()
+        for i, (r, k) in enumerate(zip(reqs, keys)):
+            delay = t_base + r["arrival"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            t = srv.submit(k, l, b, True)
+            th = threading.Thread(target=collect, args=(i, t))
+            th.start()
+            threads.append(th)
+        for th in threads:
+            th.join()
+        st_all = srv.stats()
+    ok = ok and all(d[0] == 0 for d in done)
+    lat = [d[1]["done"] - d[1]["submit"] for d in done]
+    wait = [d[1]["admit"] - d[1]["submit"] for d in done]
+    first = min(d[1]["submit"] for d in done)
+    last = max(d[1]["done"] for d in done)
+    sizes = [r["n"] for r in reqs]
+    return {"workload": f"{count} requests, Poisson 20/s, sizes log-uniform in [1e4, 1e7] "
+                        f"(min {min(sizes)}, max {max(sizes)}), l=12, b=1000, rotation, seed 5",
+            "keys": total, "hbm_budget_bytes": budget, "slots": slots,
+            "max_jobs_per_launch": per_launch, "all_ok": ok, "identical_to_plain": same,
+            "served_capacity_keys_per_s": total / t_sat,
+            "plain_keys_per_s": total / t_plain,
+            "speedup_vs_plain": t_plain / t_sat,
+            "poisson": {"keys_per_s": total / (last - first),
+                        "latency_ms_p50": _pct(lat, 50) * 1e3,
+                        "latency_ms_p99": _pct(lat, 99) * 1e3,
+                        "admission_wait_ms_p50": _pct(wait, 50) * 1e3,
+                        "admission_wait_ms_p99": _pct(wait, 99) * 1e3,
+                        "launches": st_all["launches"] - sat_stats["launches"],
+                        "peak_bytes": st_all["peak_bytes"]},
+            "plain_fifo_replay": {"latency_ms_p50": _pct(plain_lat, 50) * 1e3,
+                                  "latency_ms_p99": _pct(plain_lat, 99) * 1e3},
+            "capacity_run": {"launches": sat_stats["launches"],
+                             "peak_bytes": sat_stats["peak_bytes"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,10 +245,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-check", action="store_true",
                     help="run a plain 256 MiB device copy first (byte-counter calibration)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the batched and served workloads")
+    ap.add_argument("--served-requests", type=int, default=100)
+    ap.add_argument("--budget-gib", type=float, default=4.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--per-launch", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the construction is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+              "sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -109,8 +263,8 @@ def main():
 
     l, b, rot = WORKLOAD["leaf_size"], WORKLOAD["bucket_size"], WORKLOAD["rotation"]
     n = args.n
-    keys = keygen.fingerprints(n, WORKLOAD["seed"])
-    dev = torch.from_numpy(keys.view(np.int64)).cuda()
+    dev = keygen.fingerprints_torch(n, WORKLOAD["seed"], "cuda")
+    keys = dev.cpu().numpy().view(np.uint64)  # host copy for the CPU baseline
     torch.cuda.synchronize()
     if args.copy_check:
         src = torch.ones(1 << 25, dtype=torch.int64, device="cuda")  # 256 MiB
@@ -170,7 +324,15 @@ def main():
                      for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},
         "valu_rates": rates,
     }
+    del dev
+    if not args.headline_only:
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        out["batched"] = run_batched(recsplit, keygen, torch, max(1, args.steps), 1)
+        print("[bench] served workload", file=sys.stderr, flush=True)
+        out["served"] = run_served(recsplit, keygen, torch, args.served_requests,
+                                   args.budget_gib, args.slots, args.per_launch)
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(keys, l, b, list(range(args.cpu_buckets)))
     print(json.dumps(out), flush=True)
 

@@ -99,11 +99,14 @@ def _unit(x: np.ndarray) -> np.ndarray:
 
 
 def batched_jobs(count: int = 64, seed: int = 4, lo: float = 1e3, hi: float = 1e6,
-                 leaf_sizes=(8, 12, 16), bucket_sizes=(100, 500, 2000)):
+                 leaf_sizes=(8, 12, 16), bucket_sizes=(100, 500, 2000), draw=None):
     """Independent key-set jobs: size log-uniform in [lo, hi], leaf and bucket
     sizes each picked uniformly from the given sets.  Parameters are drawn
     first from one SplitMix64 stream, then every job's keys come from its own
-    stream seeded with (seed << 32) + job index."""
+    stream seeded with (seed << 32) + job index, through ``draw(n, seed)``
+    (default ``fingerprints``; ``fingerprints_torch`` gives the same keys on a
+    device)."""
+    draw = draw or fingerprints
     draws = splitmix64_stream(seed, 0, 3 * count).reshape(count, 3)
     u = _unit(draws[:, 0])
     sizes = np.floor(10.0 ** (math.log10(lo) + (math.log10(hi) - math.log10(lo)) * u)).astype(np.int64)
@@ -113,7 +116,7 @@ def batched_jobs(count: int = 64, seed: int = 4, lo: float = 1e3, hi: float = 1e
         l = int(leaf_sizes[int(draws[j, 1] % np.uint64(len(leaf_sizes)))])
         b = int(bucket_sizes[int(draws[j, 2] % np.uint64(len(bucket_sizes)))])
         jobs.append({"n": n, "leaf_size": l, "bucket_size": b,
-                     "keys": fingerprints(n, (seed << 32) + j)})
+                     "keys": draw(n, (seed << 32) + j)})
     return jobs
 
 

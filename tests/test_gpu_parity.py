@@ -108,6 +108,13 @@ def test_device_keys_and_determinism():
     assert rs().build(keys, 8, 100, True).serialize() == want
 
 
+def test_device_keygen_matches_host():
+    _case("keys drawn on the device equal the host draw")
+    for n, seed in ((1, 0), (100_000, 3), (77_777, (5 << 32) + 9)):
+        d = keygen.fingerprints_torch(n, seed, "cuda").cpu().numpy().view(np.uint64)
+        assert np.array_equal(d, keygen.fingerprints(n, seed)), (n, seed)
+
+
 def test_serialise_roundtrip_and_corruption():
     keys = keygen.fingerprints(10000, 13)
     _case("deserialise, n=10000 l=8 b=100")
