@@ -178,6 +178,11 @@ hipError_t after_default_stream(Context& c) {
 
 }  // namespace
 
+// A structure: its serialised words on the host; the device copy queries
+// use (with select samples) is made by the first rs_query, or by
+// rs_deserialize, which validates it there.  Builds allocate nothing per
+// structure on the device, so a finished build frees no device memory (a
+// device free waits for every stream of the device).
 struct rs_mphf {
   std::vector<uint64_t> words;
   uint64_t n = 0, nb = 0;
@@ -185,6 +190,8 @@ struct rs_mphf {
   EFLayout efc{}, efp{};
   uint64_t gr_at = 0, gr_bits = 0, gr_words = 0;
   int device = 0;
+  std::mutex dev_mu;  // guards the lazily made device copy
+  bool dev_ready = false;
   uint64_t* d_words = nullptr;
   uint64_t* d_samples = nullptr;  // samples of C, then of P
   uint64_t ns_c = 0, ns_p = 0;
@@ -246,7 +253,7 @@ int context_init(Context& c, Device* d) {
 
 void context_destroy(Context& c) {
   if (c.s) (void)hipStreamSynchronize(c.s);
-  Buffer* bs[] = {&c.arena, &c.qkeys, &c.qout, &c.sc_counts, &c.sc_prefix, &c.sc_tmp};
+  Buffer* bs[] = {&c.arena, &c.out, &c.qkeys, &c.qout, &c.sc_counts, &c.sc_prefix, &c.sc_tmp};
   for (Buffer* b : bs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -325,13 +332,14 @@ size_t batch_footprint(const std::vector<JobPlan>& jobs, uint32_t workers_max) {
 namespace {
 
 // Device copy of the serialised words plus select samples of both upper
-// vectors; checks that each upper vector holds exactly N ones.
-int attach_device(Context& c, rs_mphf* f, bool words_on_device) {
+// vectors; checks that each upper vector holds exactly N ones.  Caller holds
+// f->dev_mu.
+int attach_device(Context& c, rs_mphf* f) {
   const uint64_t nw = f->words.size();
-  if (!words_on_device) {
-    HIPCHECK(hipMalloc(&f->d_words, nw * sizeof(uint64_t)));
-    HIPCHECK(h2d(c, f->d_words, f->words.data(), nw * sizeof(uint64_t)));
-  }
+  f->d_words = nullptr;
+  f->d_samples = nullptr;
+  HIPCHECK(hipMalloc(&f->d_words, nw * sizeof(uint64_t)));
+  HIPCHECK(h2d(c, f->d_words, f->words.data(), nw * sizeof(uint64_t)));
   f->ns_c = (f->efc.N + 255) / 256;
   f->ns_p = (f->efp.N + 255) / 256;
   HIPCHECK(hipMalloc(&f->d_samples, (f->ns_c + f->ns_p + 2) * sizeof(uint64_t)));
@@ -351,6 +359,8 @@ int attach_device(Context& c, rs_mphf* f, bool words_on_device) {
     if (e.uw) HIPCHECK(d2h(c, &ones, prefix + e.uw, sizeof ones));
     if (ones != e.N) return RS_ERR_CORRUPT;
   }
+  f->device = c.dev->id;
+  f->dev_ready = true;
   return RS_OK;
 }
 
@@ -403,10 +413,8 @@ int encode_job(Context& c, const Arrays& A, JobPlan& jp, const JobInfo& info, do
     mphf_release(f);
     return code;
   };
-  if (hipMalloc(&f->d_words, nw * sizeof(uint64_t)) != hipSuccess) {
-    f->d_words = nullptr;
-    return fail(RS_ERR_OOM);
-  }
+  if (ensure(c.out, nw * sizeof(uint64_t)) != hipSuccess) return fail(RS_ERR_OOM);
+  uint64_t* const dw = static_cast<uint64_t*>(c.out.p);
   // header words, staged in the structure's host copy (alive until the copies end)
   f->words.assign(nw, 0);
   const uint64_t hdr[kHeaderWords] = {kMagic, kVersion | ((uint64_t)f->rotation << 32), jp.n,
@@ -421,33 +429,31 @@ int encode_job(Context& c, const Arrays& A, JobPlan& jp, const JobInfo& info, do
   f->words[f->gr_at] = gr_bits;
   f->words[f->gr_at + 1] = f->gr_words;
   // zero the structure, place the headers; kernels write the rest
-  if (fill_u64(f->d_words, nw, 0, s) != hipSuccess ||
-      hipMemcpyAsync(f->d_words, f->words.data(), kHeaderWords * 8, hipMemcpyHostToDevice, s) !=
+  if (fill_u64(dw, nw, 0, s) != hipSuccess ||
+      hipMemcpyAsync(dw, f->words.data(), kHeaderWords * 8, hipMemcpyHostToDevice, s) !=
           hipSuccess)
     return fail(RS_ERR_DEVICE);
   for (int i = 0; i < 2; ++i) {
     const EFLayout& e = *efs[i];
-    if (hipMemcpyAsync(f->d_words + e.at, f->words.data() + e.at, kEfHeaderWords * 8,
+    if (hipMemcpyAsync(dw + e.at, f->words.data() + e.at, kEfHeaderWords * 8,
                        hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(RS_ERR_DEVICE);
   }
-  if (hipMemcpyAsync(f->d_words + f->gr_at, f->words.data() + f->gr_at, 16, hipMemcpyHostToDevice,
-                     s) != hipSuccess)
+  if (hipMemcpyAsync(dw + f->gr_at, f->words.data() + f->gr_at, 16, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
     return fail(RS_ERR_DEVICE);
-  uint64_t* gr = f->d_words + f->gr_at + 2;
+  uint64_t* gr = dw + f->gr_at + 2;
   if (jp.total && gr_write(node_base, nb, vals, msz, jp.T->tau, pos, gr, s) != hipSuccess)
     return fail(RS_ERR_DEVICE);
   const uint64_t* xs[2] = {A.off + jp.off_base, pos};
   for (int i = 0; i < 2; ++i) {
     const EFLayout& e = *efs[i];
-    if (ef_write(xs[i], e.N, (uint32_t)e.L, f->d_words + e.at + kEfHeaderWords,
-                 f->d_words + e.at + kEfHeaderWords + e.lw, s) != hipSuccess)
+    if (ef_write(xs[i], e.N, (uint32_t)e.L, dw + e.at + kEfHeaderWords,
+                 dw + e.at + kEfHeaderWords + e.lw, s) != hipSuccess)
       return fail(RS_ERR_DEVICE);
   }
   if (hipEventRecord(c.ev[5], s) != hipSuccess) return fail(RS_ERR_DEVICE);
-  if (d2h(c, f->words.data(), f->d_words, nw * 8) != hipSuccess) return fail(RS_ERR_DEVICE);
-  int rc = attach_device(c, f, true);
-  if (rc) return fail(rc);
+  if (d2h(c, f->words.data(), dw, nw * 8) != hipSuccess) return fail(RS_ERR_DEVICE);
   if (jp.flags & RS_FLAG_KEEP_VALUES) {
     f->keep_vals.resize(jp.total);
     f->keep_base.resize(nb + 1);
@@ -673,6 +679,13 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   int search_rc = RS_OK;
   if (h_ctl.error) search_rc = -(int)h_ctl.error;
   else if (h_ctl.finished != total) search_rc = RS_ERR_DEVICE;
+  if (!search_rc)
+    for (uint32_t i = 0; i < nj; ++i) {
+      const JobPlan& j = jobs[i];
+      if (j.status || !j.total) continue;
+      HIPCHECK(work_counts(A.vals + j.node_off, A.msz + j.node_off, j.total, j.l,
+                           (j.flags & RS_FLAG_ROTATION) ? 1u : 0u, A.jinfo + i, s));
+    }
   HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
   float ms_sort = 0, ms_search = 0;
   (void)hipEventElapsedTime(&ms_sort, c.ev[1], c.ev[2]);
@@ -819,6 +832,21 @@ int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out,
   Tables* T = nullptr;
   rc = tables_for(d, f->l, &T);
   if (rc) return rc;
+  {
+    rs_mphf* g = const_cast<rs_mphf*>(f);
+    std::lock_guard<std::mutex> flock(g->dev_mu);
+    if (!g->dev_ready) {
+      rc = attach_device(*c, g);
+      if (rc) {
+        if (g->d_words) (void)hipFree(g->d_words);
+        if (g->d_samples) (void)hipFree(g->d_samples);
+        g->d_words = g->d_samples = nullptr;
+        return rc;
+      }
+    } else if (g->device != d.id) {
+      return RS_ERR_INVALID_ARG;  // the device copy lives on another device
+    }
+  }
   const Key* kd = reinterpret_cast<const Key*>(keys);
   uint64_t* od = out;
   const bool on_dev = (flags & RS_FLAG_KEYS_ON_DEVICE) != 0;
@@ -880,13 +908,13 @@ int rs_deserialize(const uint8_t* bytes, uint64_t nbytes, rs_mphf** out) {
   Context* c = default_context(&rc);
   if (c) {
     std::lock_guard<std::mutex> lock(c->mu);
-    rc = attach_device(*c, f, false);
+    std::lock_guard<std::mutex> flock(f->dev_mu);
+    rc = attach_device(*c, f);
   }
   if (rc) {
     mphf_release(f);
     return rc;
   }
-  f->device = c->dev->id;
   f->stats.n = f->n;
   f->stats.nb = f->nb;
   f->stats.gr_bits = f->gr_bits;

@@ -42,6 +42,7 @@ struct Context {
   Device* dev = nullptr;
   hipStream_t s = nullptr;
   Buffer arena;                  // working memory of the current build (default contexts)
+  Buffer out;                    // encoded words of the structure being finished
   Buffer qkeys, qout, sc_counts, sc_prefix, sc_tmp;
   hipEvent_t ev[6] = {};
   hipEvent_t upstream = nullptr;  // orders the context after the legacy default stream

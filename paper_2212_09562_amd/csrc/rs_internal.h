@@ -115,15 +115,16 @@ struct Task {
 };
 
 struct TaskState {
-  uint64_t np;    // next chunk index (high 32 bits) and chunks in flight (low 32)
-  uint64_t best;  // smallest valid value found so far (kInf: none)
-  uint32_t closed;
-  uint32_t pad0;
-  uint64_t pad1;
+  uint64_t np;      // next chunk index (high 32 bits) and chunks in flight (low 32)
+  uint64_t best;    // smallest valid value found so far (kInf: none)
+  uint32_t closed;  // set by the one worker that finalizes the task
+  uint32_t advert;  // 1 while counted in Control::long_tasks, 2 once withdrawn
+  uint64_t pad;
 };
 
 // Per-job results the kernels write: largest bucket, first error, and the
-// useful work of the search (hash evaluations the sequential definition makes).
+// useful work of the search (hash evaluations the sequential definition
+// makes), counted from the node values once the search is over.
 struct JobInfo {
   uint32_t maxm;
   uint32_t error;
@@ -141,17 +142,27 @@ struct JobDev {
   uint32_t rotation;
 };
 
+// Scheduler counters, each on its own 256-byte line: every worker updates
+// them with atomics and idle workers poll them, so sharing a line would make
+// them contend with each other.
 struct Control {
-  uint64_t head;      // next queue slot to hand out
-  uint64_t tail;      // next queue slot to fill
+  uint64_t head;  // next queue slot to hand out
+  uint64_t pad_head[31];
+  uint64_t tail;  // next queue slot to fill
+  uint64_t pad_tail[31];
   uint64_t finished;  // nodes whose value is final
-  uint64_t total;     // nodes of all jobs
-  uint32_t error;     // first RS_ERR_* seen by the search (as a positive number)
+  uint64_t pad_finished[31];
+  uint64_t long_tasks;  // searches open to helpers (see TaskState::advert)
+  uint64_t pad_long[31];
+  uint64_t total;  // nodes of all jobs (read only during the search)
+  uint32_t error;  // first RS_ERR_* seen by the search (as a positive number)
   uint32_t pad;
   // the node that raised the first error (diagnostics)
   uint64_t dbg_key_off, dbg_node, dbg_slot, dbg_np, dbg_best, dbg_chunk;
   uint32_t dbg_m, dbg_depth;
+  uint64_t pad_end[23];
 };
+static_assert(sizeof(Control) % 256 == 0, "Control lines");
 
 struct SearchParams {
   const JobDev* jobs;

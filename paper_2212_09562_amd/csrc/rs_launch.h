@@ -26,6 +26,10 @@ hipError_t queue_roots(const uint32_t* cnt, const uint64_t* off, const uint64_t*
                        uint64_t nb, uint32_t job, uint64_t key_base, uint64_t node_off, Task* tasks,
                        uint32_t* ready, Control* ctl, hipStream_t s);
 
+// Useful hash evaluations and node counts of a finished search (added to *info).
+hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, uint32_t l,
+                       uint32_t rotation, JobInfo* info, hipStream_t s);
+
 // Seed search (persistent kernel).
 hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);

@@ -186,9 +186,43 @@ __global__ void k_init_states(TaskState* st, uint64_t n) {
     t.np = 0;
     t.best = kInf;
     t.closed = 0;
-    t.pad0 = 0;
-    t.pad1 = 0;
+    t.advert = 0;
+    t.pad = 0;
     st[i] = t;
+  }
+}
+
+// Useful work of a finished search, from its node values: the hash
+// evaluations the sequential definition makes, (s+1)*m per inner node,
+// (v+1)*m per brute-force leaf and (floor(v/m)+1)*m per rotation leaf, and
+// the node counts.  One atomic per wave.
+__global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const uint32_t* msz,
+                                                     uint64_t n, uint32_t l, uint32_t rotation,
+                                                     JobInfo* info) {
+  uint64_t es = 0, el = 0, ns = 0, nl = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t m = msz[i];
+    const uint64_t v = vals[i];
+    if (m > l) {
+      es += (v + 1) * m;
+      ns += 1;
+    } else {
+      el += ((rotation ? v / m : v) + 1) * m;
+      nl += 1;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    es += __shfl_xor(es, d);
+    el += __shfl_xor(el, d);
+    ns += __shfl_xor(ns, d);
+    nl += __shfl_xor(nl, d);
+  }
+  if ((threadIdx.x & 63) == 0 && (ns | nl)) {
+    atomicAdd(&info->evals_split, es);
+    atomicAdd(&info->evals_leaf, el);
+    atomicAdd(&info->splits, ns);
+    atomicAdd(&info->leaves, nl);
   }
 }
 
@@ -292,6 +326,13 @@ hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, ui
 hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s) {
   if (!n) return hipSuccess;
   k_init_states<<<grid_for(n, 256, 4096), 256, 0, s>>>(st, n);
+  return hipGetLastError();
+}
+
+hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, uint32_t l,
+                       uint32_t rotation, JobInfo* info, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_work_counts<<<grid_for(n, 256, 2048), 256, 0, s>>>(vals, msz, n, l, rotation, info);
   return hipGetLastError();
 }
 

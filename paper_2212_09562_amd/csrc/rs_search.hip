@@ -48,6 +48,13 @@ template <typename T>
 __device__ __forceinline__ void st_relaxed(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Queue hand-off: a producer writes a task's keys and record, executes one
+// release fence, then sets the ready flags with relaxed stores; a consumer
+// polls a flag with relaxed loads and executes one acquire fence once it is
+// set, before it reads the record and the keys.  Polls therefore cost no
+// cache maintenance; each hand-off costs one write-back and one invalidation.
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 __device__ __forceinline__ bool set_error(Control* ctl, uint32_t code) {
   uint32_t expected = 0;
@@ -307,10 +314,17 @@ __device__ void stage_keys(const Task& t, const JobDev& J, const Node& c, uint64
 
 // Redistribute a split node's keys into its children's ranges of the other
 // ping-pong array (stable within each child), then queue the children.  Run
-// by wave 0; thread 0 queues.
+// by wave 0; lane 0 queues.  The queue slots are reserved with one atomic
+// before the keys move, and one release fence publishes keys and records.
 __device__ void finalize_split(const SearchParams& P, const Task& t, const JobDev& J,
                                const Node& c, uint64_t s) {
   const uint32_t lane = lane_id();
+  uint32_t nkids = 0;  // children that are stored nodes
+  for (uint32_t j = 0; j < c.k; ++j) nkids += (j + 1 < c.k ? c.unit : c.last) >= 2 ? 1u : 0u;
+  uint64_t base = 0;
+  if (lane == 0 && nkids)
+    base = __hip_atomic_fetch_add(&P.ctl->tail, (uint64_t)nkids, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
   const Key* src = J.keys[t.depth & 1] + t.key_off;
   Key* dst = J.keys[(t.depth + 1) & 1] + t.key_off;
   const uint64_t X = c.start + s;
@@ -322,63 +336,60 @@ __device__ void finalize_split(const SearchParams& P, const Task& t, const JobDe
     const uint32_t p = reduce(hash_top(key.w1, X), c.m);
     uint32_t ch = c.kind == kBinary ? (p >= c.unit ? 1u : 0u) : p / c.unit;
     if (!v) ch = 0xFFFFFFFFu;
-    const uint32_t base = (uint32_t)__shfl((int)run, v ? (int)ch : 0);
+    const uint32_t at0 = (uint32_t)__shfl((int)run, v ? (int)ch : 0);
     uint32_t rank = 0;
     for (uint32_t j = 0; j < c.k; ++j) {
       const uint64_t mk = __ballot(ch == j);
       if (ch == j) rank = (uint32_t)__popcll(mk & mask_below(lane));
       if (lane == j) run += (uint32_t)__popcll(mk);
     }
-    const uint32_t at = ch * c.unit + base + rank;
+    const uint32_t at = ch * c.unit + at0 + rank;
     if (v && at < c.m) dst[at] = key;
   }
   const bool good = lane >= c.k || run == (lane + 1 < c.k ? c.unit : c.last);
   const bool all_good = __ballot(!good) == 0;
-  __threadfence();
+  bool queued = false;
   if (lane == 0) {
     if (!all_good) set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
     J.vals[t.node] = s;
     J.msz[t.node] = c.m;
-    __hip_atomic_fetch_add(&J.info->evals_split, (s + 1) * c.m, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&J.info->splits, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t child_node = t.node + 1;
-    for (uint32_t j = 0; j < c.k; ++j) {
-      const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
-      if (sz >= 2 && t.depth + 1 >= kMaxDepth) {
-        set_error(P.ctl, (uint32_t)(-RS_ERR_UNSUPPORTED));
-      } else if (sz >= 2) {
-        const uint64_t slot = __hip_atomic_fetch_add(&P.ctl->tail, 1ull, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        if (slot >= P.ctl->total) {
-          set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
-        } else {
+    if (nkids && t.depth + 1 >= kMaxDepth) {
+      set_error(P.ctl, (uint32_t)(-RS_ERR_UNSUPPORTED));
+    } else if (nkids && base + nkids > P.ctl->total) {
+      set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
+    } else {
+      queued = true;
+      uint64_t child_node = t.node + 1, slot = base;
+      for (uint32_t j = 0; j < c.k; ++j) {
+        const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
+        if (sz >= 2) {
           Task ct;
           ct.key_off = t.key_off + (uint64_t)j * c.unit;
           ct.node = child_node;
           ct.m = sz;
           ct.depth = (uint16_t)(t.depth + 1);
           ct.job = t.job;
-          P.tasks[slot] = ct;
-          st_release(&P.ready[slot], 1u);
+          P.tasks[slot++] = ct;
         }
+        child_node += J.nodecnt[sz];
       }
-      child_node += J.nodecnt[sz];
     }
-    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  fence_release();  // keys (every lane) and task records before the flags
+  if (lane == 0) {
+    if (queued)
+      for (uint32_t i = 0; i < nkids; ++i) st_relaxed(&P.ready[base + i], 1u);
+    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
+// A leaf's value is read only after the launch: no ordering needed.
 __device__ void finalize_leaf(const SearchParams& P, const Task& t, const JobDev& J,
                               const Node& c, uint64_t v) {
   if (threadIdx.x == 0) {
     J.vals[t.node] = v;
     J.msz[t.node] = c.m;
-    const uint64_t att = c.rotation ? v / c.m : v;
-    __hip_atomic_fetch_add(&J.info->evals_leaf, (att + 1) * c.m, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&J.info->leaves, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -478,6 +489,15 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
           sh.fin = release_chunk(st) ? 1u : 0u;
         } else {
           chunk = ci;
+          if (ci == kHelpAfter && best == kInf) {
+            // a long search: count it so idle workers look for it
+            uint32_t expected = 0;
+            if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 1u, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+              __hip_atomic_fetch_add(&P.ctl->long_tasks, 1ull, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+            wait_memory();  // counted before this chunk can be dropped
+          }
         }
       }
       sh.chunk = chunk;
@@ -497,7 +517,14 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       __syncthreads();
     }
     if (sh.fin) {
-      if (tid == 0) sh.fin_value = ld_relaxed(&st->best);
+      if (tid == 0) {
+        sh.fin_value = ld_relaxed(&st->best);
+        uint32_t expected = 1;
+        if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 2u, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          __hip_atomic_fetch_add(&P.ctl->long_tasks, ~0ull, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
       __syncthreads();
       const uint64_t v = sh.fin_value;
       if (tid < 64) finalize_split(P, t, J, c, v);
@@ -515,28 +542,33 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
   __shared__ Shared sh;
   const uint32_t tid = threadIdx.x;
   const uint32_t g = blockIdx.x;
+  const uint64_t total = P.ctl->total;
   uint64_t my_q = kNoSlot;  // thread 0 only
   uint64_t last_finished = 0, idle_since = 0;
+  uint32_t idle = 0;  // thread 0: consecutive rounds without work
   if (tid == 0) sh.iter = 0;
   __syncthreads();
   for (;;) {
     __syncthreads();  // every thread has read the previous decision
     if (tid == 0) {
-      uint32_t act = kActScan;
+      uint32_t act = kActRetry;
       if (ld_relaxed(&P.ctl->error) != 0) {
         act = kActExit;
       } else {
         if (my_q == kNoSlot) {
           const uint64_t q = __hip_atomic_fetch_add(&P.ctl->head, 1ull, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
-          my_q = q < P.ctl->total ? q : kExhausted;
+          my_q = q < total ? q : kExhausted;
         }
-        if (my_q < kExhausted && ld_acquire(&P.ready[my_q]) != 0) {
+        if (my_q < kExhausted && ld_relaxed(&P.ready[my_q]) != 0) {
+          fence_acquire();
           act = kActOwn;
           sh.arg = my_q;
           my_q = kNoSlot;
-        } else if (my_q == kExhausted && ld_acquire(&P.ctl->finished) >= P.ctl->total) {
+        } else if (my_q == kExhausted && ld_relaxed(&P.ctl->finished) >= total) {
           act = kActExit;
+        } else if (ld_relaxed(&P.ctl->long_tasks) != 0) {
+          act = kActScan;
         }
       }
       sh.action = act;
@@ -547,12 +579,13 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
     uint32_t act = sh.action;
     if (act == kActExit) break;
     if (act == kActScan) {
+      // look for a long search among up to 256 workers, from a rotating start
       const uint32_t W = P.workers;
       const uint32_t rot = (g * 2654435761u + sh.iter * 40503u) % W;
-      for (uint32_t i = tid; i < W; i += kWG) {
-        uint32_t idx = i + rot;
+      if (tid < W) {
+        uint32_t idx = tid + rot;
         if (idx >= W) idx -= W;
-        if (ld_relaxed(&P.active[idx]) >= 0) atomicMin(&sh.pick, (int32_t)i);
+        if (ld_relaxed(&P.active[idx]) >= 0) atomicMin(&sh.pick, (int32_t)tid);
       }
       __syncthreads();
       if (tid == 0) {
@@ -561,41 +594,46 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
           uint32_t idx = (uint32_t)sh.pick + rot;
           if (idx >= W) idx -= W;
           const int32_t a = ld_relaxed(&P.active[idx]);
-          if (a >= 0 && ld_acquire(&P.ready[a]) != 0) {
+          if (a >= 0 && ld_relaxed(&P.ready[a]) != 0) {
             // join only searches that are long already: a task that ends in
             // its first chunks gains nothing from more workers
             const TaskState* ts = P.states + a;
             if ((ld_relaxed(&ts->np) >> 32) >= kHelpAfter && ld_relaxed(&ts->best) == kInf) {
+              fence_acquire();
               next = kActHelp;
               sh.arg = (uint64_t)a;
             }
           }
         }
-        if (next == kActRetry) {
-          // bug guard: no node finished for stall_ticks of the 100 MHz clock
-          const uint64_t fin = ld_relaxed(&P.ctl->finished);
-          const uint64_t now = __builtin_amdgcn_s_memrealtime();
-          if (fin != last_finished || idle_since == 0) {
-            last_finished = fin;
-            idle_since = now;
-          } else if (now - idle_since > P.stall_ticks) {
-            set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
-          }
-          __builtin_amdgcn_s_sleep(8);
-        } else {
-          idle_since = 0;
-        }
         sh.action = next;
       }
       __syncthreads();
       act = sh.action;
-      if (act == kActRetry) continue;
+    }
+    if (act == kActRetry) {
+      if (tid == 0) {
+        // bug guard: no node finished for stall_ticks of the 100 MHz clock
+        const uint64_t fin = ld_relaxed(&P.ctl->finished);
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        if (fin != last_finished || idle_since == 0) {
+          last_finished = fin;
+          idle_since = now;
+        } else if (now - idle_since > P.stall_ticks) {
+          set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
+        }
+        // back off while idle: 1, 2, 4, 8 sleeps of 16 x 64 cycles
+        const uint32_t naps = 1u << (idle < 3 ? idle : 3);
+        for (uint32_t i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(16);
+        ++idle;
+      }
+      continue;
     }
     const uint64_t slot = sh.arg;
     if (tid == 0) {
       sh.task = P.tasks[slot];
       if (act == kActOwn) st_relaxed(&P.active[g], (int32_t)slot);
       idle_since = 0;
+      idle = 0;
     }
     __syncthreads();
     run_task(P, sh, s_keys, slot, act == kActOwn, my_q);
