@@ -144,14 +144,56 @@ def _pct(xs, q):
     return xs[min(len(xs) - 1, int(math.ceil(q / 100.0 * len(xs))) - 1)]
 
 
-def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch):
+def _poisson_plain(recsplit, reqs, keys, l, b):
+    """Plain rs_build calls, one request at a time in arrival order, each
+    started no earlier than its arrival time: latency = done - arrival."""
+    lat = []
+    t_base = time.perf_counter()
+    for r, k in zip(reqs, keys):
+        delay = t_base + r["arrival"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        f = recsplit.build(k, l, b, True)
+        lat.append(time.perf_counter() - (t_base + r["arrival"]))
+        f.free()
+    return lat, time.perf_counter() - (t_base + reqs[0]["arrival"])
+
+
+def _poisson_served(srv, reqs, keys, l, b):
+    """The server fed at the arrival times: latency = done - submit."""
+    import threading
+
+    done = [None] * len(reqs)
+
+    def collect(i, t):
+        f, st, tm = srv.wait(t)
+        done[i] = (st, tm)
+        if f is not None:
+            f.free()
+
+    threads = []
+    t_base = time.perf_counter()
+    for i, (r, k) in enumerate(zip(reqs, keys)):
+        delay = t_base + r["arrival"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        th = threading.Thread(target=collect, args=(i, srv.submit(k, l, b, True)))
+        th.start()
+        threads.append(th)
+    for th in threads:
+        th.join()
+    lat = [d[1]["done"] - d[1]["submit"] for d in done]
+    wait = [d[1]["admit"] - d[1]["submit"] for d in done]
+    span = max(d[1]["done"] for d in done) - min(d[1]["submit"] for d in done)
+    return lat, wait, span, all(d[0] == 0 for d in done)
+
+
+def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, reserve):
     """Construction requests with Poisson arrivals (20 per second) and sizes
     log-uniform in [10^4, 10^7] keys, l = 12, b = 1000, rotation fitting
-    (seed 5), keys resident in HBM.  Three runs over the same requests:
-    plain rs_build calls one after another; the server with every request
-    queued at once (its capacity); the server fed at the arrival times
-    (latency).  A single-queue server using plain launches is replayed from
-    the measured plain build times for the same arrivals."""
+    (seed 5), keys resident in HBM.  Capacity (every request queued at once)
+    and latency (requests fed at their arrival times) of the server, against
+    the same requests built by plain rs_build calls one at a time."""
     reqs = keygen.served_requests(count, seed=5)
     keys = [keygen.fingerprints_torch(r["n"], r["seed"], "cuda") for r in reqs]
     torch.cuda.synchronize()
@@ -159,23 +201,17 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch):
     l, b = 12, 1000
     budget = int(budget_gib * (1 << 30))
     recsplit.build(keys[0], l, b, True).free()  # warm-up
-    # plain launches, one request at a time
-    plain_s, plain_f = [], []
+    # plain launches back to back
+    plain_f = []
     t0 = time.perf_counter()
     for k in keys:
-        a = time.perf_counter()
         plain_f.append(recsplit.build(k, l, b, True))
-        plain_s.append(time.perf_counter() - a)
     t_plain = time.perf_counter() - t0
     plain_digest = [hashlib.sha256(f.serialize()).digest() for f in plain_f]
     del plain_f
-    # FIFO single-queue server with plain launches, replayed at the arrival times
-    fin, plain_lat = 0.0, []
-    for r, s in zip(reqs, plain_s):
-        fin = max(fin, r["arrival"]) + s
-        plain_lat.append(fin - r["arrival"])
-    with recsplit.Server(budget, max_slots=slots, max_jobs_per_launch=per_launch) as srv:
-        # capacity: every request queued at once
+    plain_lat, plain_span = _poisson_plain(recsplit, reqs, keys, l, b)
+    with recsplit.Server(budget, max_slots=slots, max_jobs_per_launch=per_launch,
+                         reserve_per_cu=reserve) as srv:
         t0 = time.perf_counter()
         tickets = [srv.submit(k, l, b, True) for k in keys]
         res = [srv.wait(t) for t in tickets]
@@ -185,52 +221,26 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch):
         ok = all(st == 0 for (_, st, _) in res)
         del res
         sat_stats = srv.stats()
-        # arrivals at their Poisson times
-        import threading
-
-        done = [None] * len(reqs)
-
-        def collect(i, t):
-            f, st, tm = srv.wait(t)
-            done[i] = (st, tm)
-            if f is not None:
-                f.free()
-
-        threads = []
-        t_base = time.perf_counter()
-        for i, (r, k) in enumerate(zip(reqs, keys)):
-            delay = t_base + r["arrival"] - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            t = srv.submit(k, l, b, True)
-            th = threading.Thread(target=collect, args=(i, t))
-            th.start()
-            threads.append(th)
-        for th in threads:
-            th.join()
+        lat, wait, span, ok2 = _poisson_served(srv, reqs, keys, l, b)
         st_all = srv.stats()
-    ok = ok and all(d[0] == 0 for d in done)
-    lat = [d[1]["done"] - d[1]["submit"] for d in done]
-    wait = [d[1]["admit"] - d[1]["submit"] for d in done]
-    first = min(d[1]["submit"] for d in done)
-    last = max(d[1]["done"] for d in done)
     sizes = [r["n"] for r in reqs]
     return {"workload": f"{count} requests, Poisson 20/s, sizes log-uniform in [1e4, 1e7] "
                         f"(min {min(sizes)}, max {max(sizes)}), l=12, b=1000, rotation, seed 5",
             "keys": total, "hbm_budget_bytes": budget, "slots": slots,
-            "max_jobs_per_launch": per_launch, "all_ok": ok, "identical_to_plain": same,
+            "max_jobs_per_launch": per_launch, "reserve_per_cu": reserve,
+            "all_ok": ok and ok2, "identical_to_plain": same,
             "served_capacity_keys_per_s": total / t_sat,
-            "plain_keys_per_s": total / t_plain,
-            "speedup_vs_plain": t_plain / t_sat,
-            "poisson": {"keys_per_s": total / (last - first),
-                        "latency_ms_p50": _pct(lat, 50) * 1e3,
-                        "latency_ms_p99": _pct(lat, 99) * 1e3,
-                        "admission_wait_ms_p50": _pct(wait, 50) * 1e3,
-                        "admission_wait_ms_p99": _pct(wait, 99) * 1e3,
-                        "launches": st_all["launches"] - sat_stats["launches"],
-                        "peak_bytes": st_all["peak_bytes"]},
-            "plain_fifo_replay": {"latency_ms_p50": _pct(plain_lat, 50) * 1e3,
-                                  "latency_ms_p99": _pct(plain_lat, 99) * 1e3},
+            "plain_capacity_keys_per_s": total / t_plain,
+            "capacity_speedup_vs_plain": t_plain / t_sat,
+            "poisson_served": {"keys_per_s": total / span,
+                               "latency_ms_p50": _pct(lat, 50) * 1e3,
+                               "latency_ms_p99": _pct(lat, 99) * 1e3,
+                               "admission_wait_ms_p50": _pct(wait, 50) * 1e3,
+                               "admission_wait_ms_p99": _pct(wait, 99) * 1e3,
+                               "launches": st_all["launches"] - sat_stats["launches"]},
+            "poisson_plain": {"keys_per_s": total / plain_span,
+                              "latency_ms_p50": _pct(plain_lat, 50) * 1e3,
+                              "latency_ms_p99": _pct(plain_lat, 99) * 1e3},
             "capacity_run": {"launches": sat_stats["launches"],
                              "peak_bytes": sat_stats["peak_bytes"]}}
 
@@ -249,8 +259,9 @@ def main():
                     help="skip the batched and served workloads")
     ap.add_argument("--served-requests", type=int, default=100)
     ap.add_argument("--budget-gib", type=float, default=4.0)
-    ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--per-launch", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--per-launch", type=int, default=8)
+    ap.add_argument("--reserve-per-cu", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the construction is not "
@@ -330,7 +341,8 @@ def main():
         out["batched"] = run_batched(recsplit, keygen, torch, max(1, args.steps), 1)
         print("[bench] served workload", file=sys.stderr, flush=True)
         out["served"] = run_served(recsplit, keygen, torch, args.served_requests,
-                                   args.budget_gib, args.slots, args.per_launch)
+                                   args.budget_gib, args.slots, args.per_launch,
+                                   args.reserve_per_cu)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(keys, l, b, list(range(args.cpu_buckets)))

@@ -130,6 +130,9 @@ typedef struct {
   uint64_t hbm_budget_bytes;    /* device pool size, >= 1 MiB */
   uint32_t max_slots;           /* concurrent builds, 1..64 */
   uint32_t max_jobs_per_launch; /* requests per search launch, >= 1 */
+  uint32_t reserve_per_cu;      /* search workgroups per compute unit each launch leaves
+                                   free, so a build admitted while another runs starts
+                                   at once (0: every launch takes the whole device) */
 } rs_server_config;
 
 typedef struct {
@@ -163,6 +166,29 @@ int rs_server_poll(rs_server *s, uint64_t ticket, int wait, rs_mphf **out, int *
 int rs_server_get_stats(rs_server *s, rs_server_stats *st);
 
 void rs_server_destroy(rs_server *s);
+
+/*
+ * Search schedule: how the seed search hands out attempts, never what it
+ * finds (every schedule gives the same structure).  A launch is small when it
+ * has fewer than small_tasks_per_worker nodes per worker; small launches use
+ * the *_small settings (short chunks that idle workers share early), others
+ * the *_large ones.
+ *   rounds_split_*: rounds of 256 attempts per claimed chunk of a split search, >= 1
+ *   help_after_*:   chunks a split search must have handed out before idle
+ *                   workers join it, >= 1
+ *   max_workers:    cap on the persistent grid (0: the occupancy limit)
+ * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
+ * restores the defaults; RS_ERR_INVALID_ARG for a zero count.
+ */
+typedef struct {
+  uint32_t rounds_split_small, help_after_small;
+  uint32_t rounds_split_large, help_after_large;
+  uint32_t small_tasks_per_worker;
+  uint32_t max_workers;
+} rs_schedule;
+
+int rs_set_schedule(const rs_schedule *s);
+int rs_get_schedule(rs_schedule *s);
 
 /*
  * Evaluate the function on n keys (Sec. 2.2 "Query": bucket, tree descent,

@@ -1,0 +1,103 @@
+"""Autotuner of the seed-search schedule (rs_set_schedule).
+
+The schedule decides how the persistent search kernel hands out attempts --
+chunk length of a split search, how soon idle workers join a long search,
+grid size -- and never what it finds: every schedule yields the same
+structure.  Small launches (few nodes per worker, e.g. one small request)
+are latency bound and want short chunks that idle workers share early;
+large launches are throughput bound and want long chunks with little
+scheduling traffic.
+
+``tune()`` times the search kernel (HIP events around the launch, reported
+in the build statistics) on synthetic key sets for every candidate setting
+of each launch class and returns the fastest schedule; ``python -m
+paper_2212_09562_amd.autotune`` prints it as JSON, and ``apply()`` installs
+a schedule for the process.  The library's built-in defaults are this
+tuner's result on an MI355X.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import statistics
+
+from . import keygen, recsplit
+
+# (n, leaf size, bucket size) of the key sets each launch class is timed on
+SMALL_SETS = [(10_000, 12, 1000), (30_000, 12, 1000), (20_000, 16, 2000)]
+LARGE_SETS = [(1_000_000, 12, 1000), (10_000_000, 12, 1000), (1_000_000, 8, 100),
+              (300_000, 16, 2000)]
+ROUNDS = (1, 2, 4, 8, 16, 32)
+HELP_AFTER = (1, 2, 4)
+
+
+def _time_sets(sets, keys, reps):
+    total = 0.0
+    for (n, l, b), k in zip(sets, keys):
+        ms = []
+        for _ in range(reps):
+            f = recsplit.build(k, l, b, True)
+            ms.append(f.stats()["ms_search"])
+            f.free()
+        total += statistics.median(ms)
+    return total
+
+
+def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, rounds=ROUNDS, help_after=HELP_AFTER,
+         reps=3, seed=11, log=None):
+    """Fastest (rounds_split, help_after) per launch class; returns the schedule
+    dict and the timing table."""
+    import torch
+
+    base = recsplit.set_schedule(None)
+    keys = {id(s): [keygen.fingerprints_torch(n, seed + i, "cuda") for i, (n, _, _) in enumerate(s)]
+            for s in (small_sets, large_sets)}
+    torch.cuda.synchronize()
+    table = {}
+    best = dict(base)
+    try:
+        for cls, sets in (("small", small_sets), ("large", large_sets)):
+            ks = keys[id(sets)]
+            # force every set into this class
+            force = {"small_tasks_per_worker": 1 << 30} if cls == "small" else {
+                "small_tasks_per_worker": 1}
+            _time_sets(sets, ks, 1)  # warm-up
+            results = []
+            for r in rounds:
+                for h in help_after:
+                    recsplit.set_schedule(base, **force, **{f"rounds_split_{cls}": r,
+                                                            f"help_after_{cls}": h})
+                    t = _time_sets(sets, ks, reps)
+                    results.append((t, r, h))
+                    if log:
+                        log(f"{cls} rounds_split={r} help_after={h}: {t:.3f} ms")
+            results.sort()
+            table[cls] = [{"ms": t, "rounds_split": r, "help_after": h} for t, r, h in results]
+            best[f"rounds_split_{cls}"] = results[0][1]
+            best[f"help_after_{cls}"] = results[0][2]
+    finally:
+        recsplit.set_schedule(None)
+    return best, table
+
+
+def apply(schedule: dict) -> dict:
+    """Install a schedule for this process."""
+    return recsplit.set_schedule(None, **schedule) if schedule else recsplit.set_schedule(None)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", help="write the schedule and timing table as JSON")
+    args = ap.parse_args()
+    best, table = tune(reps=args.reps, log=lambda s: print(s, flush=True))
+    out = {"schedule": best, "timings_ms": table, "defaults": recsplit.get_schedule()}
+    text = json.dumps(out, indent=1)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text + "\n")
+    print(json.dumps({"schedule": best}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,15 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
+constexpr rs_schedule kDefaultSchedule = {1, 1, 1, 2, 8, 0};  // autotune.py on an MI355X
+rs_schedule g_schedule = kDefaultSchedule;
+std::mutex g_schedule_mu;
+
+rs_schedule current_schedule() {
+  std::lock_guard<std::mutex> lock(g_schedule_mu);
+  return g_schedule;
+}
+
 int tables_for(Device& d, uint32_t l, Tables** out) {
   std::lock_guard<std::mutex> lock(d.mu);
   Tables& t = d.tables[l];
@@ -510,12 +519,10 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     int rc = tables_for(d, j.l, &j.T);
     if (rc) return rc;
   }
+  const rs_schedule sched = current_schedule();
   const uint32_t wmax = max_workers(d);
   uint32_t workers = workers_cap && workers_cap < wmax ? workers_cap : wmax;
-  if (const char* ew = getenv("RS_WORKERS")) {
-    const int w = atoi(ew);
-    if (w > 0 && (uint32_t)w < workers) workers = (uint32_t)w;
-  }
+  if (sched.max_workers && sched.max_workers < workers) workers = sched.max_workers;
   if (batch_footprint(jobs, wmax) > region_bytes) return RS_ERR_OOM;
   Carver cv{static_cast<char*>(region), region_bytes};
   Arrays A;
@@ -650,11 +657,10 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     P.start = d.start;
     P.workers = workers;
     P.stage_cap = maxm;
-    // rounds of 256 attempts per claimed chunk of a split search (a schedule
-    // setting: the result does not depend on it)
-    const char* e2 = getenv("RS_ROUNDS_SPLIT");
-    P.rounds_split = e2 ? (uint32_t)atoi(e2) : 16u;
-    if (P.rounds_split < 1) P.rounds_split = 1;
+    // chunking of split searches (the result does not depend on it)
+    const bool small = total < (uint64_t)sched.small_tasks_per_worker * workers;
+    P.rounds_split = small ? sched.rounds_split_small : sched.rounds_split_large;
+    P.help_after = small ? sched.help_after_small : sched.help_after_large;
     P.cap_shift = 10;
     P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
     HIPCHECK(hipEventRecord(c.ev[3], s));
@@ -940,6 +946,22 @@ int rs_get_stats(const rs_mphf* f, rs_stats* st) {
 }
 
 void rs_free(rs_mphf* f) { mphf_release(f); }
+
+int rs_set_schedule(const rs_schedule* sc) {
+  rs_schedule v = sc ? *sc : kDefaultSchedule;
+  if (!v.rounds_split_small || !v.help_after_small || !v.rounds_split_large ||
+      !v.help_after_large || !v.small_tasks_per_worker)
+    return RS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_schedule_mu);
+  g_schedule = v;
+  return RS_OK;
+}
+
+int rs_get_schedule(rs_schedule* sc) {
+  if (!sc) return RS_ERR_INVALID_ARG;
+  *sc = current_schedule();
+  return RS_OK;
+}
 
 const char* rs_strerror(int code) {
   switch (code) {

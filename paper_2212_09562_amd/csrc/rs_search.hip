@@ -28,7 +28,6 @@ namespace {
 constexpr uint64_t kStop = ~0ull;
 constexpr uint64_t kNoSlot = ~0ull;
 constexpr uint64_t kExhausted = ~0ull - 1;
-constexpr uint64_t kHelpAfter = 2;  // chunks a task must have used before others join it
 
 enum : uint32_t { kActExit = 0, kActOwn = 1, kActHelp = 2, kActScan = 3, kActRetry = 4 };
 
@@ -489,7 +488,7 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
           sh.fin = release_chunk(st) ? 1u : 0u;
         } else {
           chunk = ci;
-          if (ci == kHelpAfter && best == kInf) {
+          if (ci == P.help_after && best == kInf) {
             // a long search: count it so idle workers look for it
             uint32_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 1u, __ATOMIC_RELAXED,
@@ -598,7 +597,7 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
             // join only searches that are long already: a task that ends in
             // its first chunks gains nothing from more workers
             const TaskState* ts = P.states + a;
-            if ((ld_relaxed(&ts->np) >> 32) >= kHelpAfter && ld_relaxed(&ts->best) == kInf) {
+            if ((ld_relaxed(&ts->np) >> 32) >= P.help_after && ld_relaxed(&ts->best) == kInf) {
               fence_acquire();
               next = kActHelp;
               sh.arg = (uint64_t)a;

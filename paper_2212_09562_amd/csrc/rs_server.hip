@@ -96,6 +96,7 @@ struct rs_server {
   uint64_t next_ticket = 1;
   bool stopping = false;
   uint32_t workers_max = 0;
+  uint32_t workers_cap = 0;  // search grid of each launch
   rs_server_stats st{};
   size_t in_use = 0;
   size_t usable = 0;  // pool bytes in whole regions
@@ -167,7 +168,7 @@ void slot_loop(rs_server* S, uint32_t slot) {
         S->cv_work.wait(lock);
       }
     }
-    int rc = build_jobs(c, plan, S->pool + off, bytes, 0);
+    int rc = build_jobs(c, plan, S->pool + off, bytes, S->workers_cap);
     if (rc) {
       (void)hipStreamSynchronize(c.s);
       (void)hipGetLastError();
@@ -215,6 +216,11 @@ int rs_server_create(const rs_server_config* cfg, rs_server** out) {
     return rc;
   }
   S->workers_max = max_workers(*S->dev);
+  {
+    const uint64_t cus = (uint64_t)S->dev->cus;
+    const uint64_t keep = (uint64_t)cfg->reserve_per_cu * cus;
+    S->workers_cap = keep + cus <= S->workers_max ? (uint32_t)(S->workers_max - keep) : (uint32_t)cus;
+  }
   if (hipMalloc(reinterpret_cast<void**>(&S->pool), cfg->hbm_budget_bytes) != hipSuccess) {
     delete S;
     return RS_ERR_OOM;

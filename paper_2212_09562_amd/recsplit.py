@@ -89,9 +89,22 @@ _lib.rs_build_batch.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POI
 _lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint32) for k in ("rounds_split_small", "help_after_small",
+                                                "rounds_split_large", "help_after_large",
+                                                "small_tasks_per_worker", "max_workers")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib.rs_set_schedule.argtypes = [ctypes.POINTER(Schedule)]
+_lib.rs_get_schedule.argtypes = [ctypes.POINTER(Schedule)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
-                ("max_jobs_per_launch", ctypes.c_uint32)]
+                ("max_jobs_per_launch", ctypes.c_uint32), ("reserve_per_cu", ctypes.c_uint32)]
 
 
 class RequestTimes(ctypes.Structure):
@@ -125,7 +138,8 @@ _lib.rs_strerror.argtypes = [ctypes.c_int]
 _lib.rs_strerror.restype = ctypes.c_char_p
 for _f in ("rs_build", "rs_build_batch", "rs_query", "rs_serialize", "rs_deserialize",
            "rs_debug_node_values", "rs_get_stats", "rs_calibrate_valu", "rs_server_create",
-           "rs_server_submit", "rs_server_poll", "rs_server_get_stats"):
+           "rs_server_submit", "rs_server_poll", "rs_server_get_stats", "rs_set_schedule",
+           "rs_get_schedule"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -232,8 +246,9 @@ class Server:
     submit() queues a request and returns its ticket; the key array is kept
     alive here until its result is collected with poll()/wait()."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, max_jobs_per_launch: int = 16):
-        cfg = ServerConfig(hbm_budget_bytes, max_slots, max_jobs_per_launch)
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, max_jobs_per_launch: int = 16,
+                 reserve_per_cu: int = 1):
+        cfg = ServerConfig(hbm_budget_bytes, max_slots, max_jobs_per_launch, reserve_per_cu)
         h = ctypes.c_void_p()
         _check(_lib.rs_server_create(ctypes.byref(cfg), ctypes.byref(h)), "rs_server_create")
         self._h = h
@@ -284,6 +299,26 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+def get_schedule() -> dict:
+    """The search schedule (rs_get_schedule)."""
+    sc = Schedule()
+    _check(_lib.rs_get_schedule(ctypes.byref(sc)), "rs_get_schedule")
+    return sc.as_dict()
+
+
+def set_schedule(schedule=None, **changes) -> dict:
+    """rs_set_schedule: None (and no changes) restores the defaults; otherwise
+    the given fields replace those of ``schedule`` (default: the current one).
+    Returns the schedule now in force."""
+    if schedule is None and not changes:
+        _check(_lib.rs_set_schedule(None), "rs_set_schedule")
+        return get_schedule()
+    sc = dict(schedule or get_schedule())
+    sc.update(changes)
+    _check(_lib.rs_set_schedule(ctypes.byref(Schedule(**sc))), "rs_set_schedule")
+    return get_schedule()
 
 
 def deserialize(data: bytes) -> MPHF:

@@ -89,3 +89,22 @@ def test_batched_configuration_same_as_solo():
             recs, _ = oracle.build_buckets(j["keys"], j["leaf_size"], j["bucket_size"], True, [0])
             for (bk, size, vals, words, nbits) in recs:
                 assert np.array_equal(outs[i].node_values(bk), vals), (i, bk)
+
+
+def test_autotuner_runs_and_leaves_defaults():
+    from paper_2212_09562_amd import autotune
+
+    _case("autotune on tiny sets")
+    before = rs().get_schedule()
+    best, table = autotune.tune(small_sets=[(5000, 12, 1000)], large_sets=[(20000, 8, 100)],
+                                rounds=(1, 4), help_after=(1, 2), reps=1)
+    assert rs().get_schedule() == before
+    assert best["rounds_split_small"] in (1, 4) and best["help_after_large"] in (1, 2)
+    assert len(table["small"]) == 4 and len(table["large"]) == 4
+    keys = keygen.fingerprints(20000, 5)
+    want = rs().build(keys, 8, 100, True).serialize()
+    try:
+        autotune.apply(best)
+        assert rs().build(keys, 8, 100, True).serialize() == want
+    finally:
+        rs().set_schedule(None)

@@ -9,7 +9,6 @@ configurations follow at full size (the l = 16, b = 2000 build on a sample
 of buckets the oracle can afford).
 """
 import math
-import os
 
 import numpy as np
 import pytest
@@ -92,19 +91,21 @@ def test_device_keys_and_determinism():
     r = f.query(dk)
     torch.cuda.synchronize()
     assert np.array_equal(r.cpu().numpy().view(np.uint64), oracle.query(want, keys))
-    # a shuffled copy and a different chunk schedule give the same bytes
+    # a shuffled copy and other chunk schedules give the same bytes
     perm = np.random.default_rng(0).permutation(len(keys))
-    old = {k: os.environ.get(k) for k in ("RS_ROUNDS_SPLIT", "RS_WORKERS")}
+    k16 = keys[:2500]
+    want16 = oracle.build(k16, 16, 2000, True)[0]
     try:
-        os.environ["RS_ROUNDS_SPLIT"] = "3"
-        os.environ["RS_WORKERS"] = "37"
-        assert rs().build(keys[perm], 8, 100, True).serialize() == want
+        for sched in ({"rounds_split_small": 3, "rounds_split_large": 3, "help_after_small": 1,
+                       "help_after_large": 1, "max_workers": 37},
+                      {"rounds_split_small": 1, "rounds_split_large": 64, "help_after_small": 5,
+                       "help_after_large": 1, "small_tasks_per_worker": 1000}):
+            rs().set_schedule(None)
+            rs().set_schedule(**sched)
+            assert rs().build(keys[perm], 8, 100, True).serialize() == want
+            assert rs().build(k16, 16, 2000, True).serialize() == want16
     finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+        rs().set_schedule(None)
     assert rs().build(keys, 8, 100, True).serialize() == want
 
 

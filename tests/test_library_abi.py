@@ -91,7 +91,20 @@ def test_server_config_rejected_before_any_device_call():
     lib = recsplit.library()
     h = ctypes.c_void_p()
     for budget, slots in ((1 << 30, 0), (1 << 30, 65), (1000, 2)):
-        cfg = recsplit.ServerConfig(budget, slots, 4)
+        cfg = recsplit.ServerConfig(budget, slots, 4, 1)
         assert lib.rs_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
     assert lib.rs_server_create(None, ctypes.byref(h)) == -1
     assert recsplit.strerror(recsplit.RS_PENDING) != "unknown error"
+
+
+def test_schedule_defaults_and_validation():
+    from paper_2212_09562_amd import recsplit
+
+    d = recsplit.set_schedule(None)
+    assert all(d[k] >= 1 for k in d if k != "max_workers")
+    with pytest.raises(recsplit.RecSplitError) as e:
+        recsplit.set_schedule(rounds_split_large=0)
+    assert e.value.code == -1
+    assert recsplit.get_schedule() == d
+    assert recsplit.set_schedule(rounds_split_large=7)["rounds_split_large"] == 7
+    assert recsplit.set_schedule(None) == d
