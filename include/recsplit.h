@@ -169,20 +169,22 @@ void rs_server_destroy(rs_server *s);
 
 /*
  * Search schedule: how the seed search hands out attempts, never what it
- * finds (every schedule gives the same structure).  A launch is small when it
- * has fewer than small_tasks_per_worker nodes per worker; small launches use
- * the *_small settings (short chunks that idle workers share early), others
- * the *_large ones.
- *   rounds_split_*: rounds of 256 attempts per claimed chunk of a split search, >= 1
+ * finds (every schedule gives the same structure).  A split search is handed
+ * out in chunks of 2^max(0, min(8, tau - chunk_shift)) rounds of 256
+ * attempts, tau being the node's Rice parameter (about log2 of its expected
+ * attempts), so long searches take few claims and short ones stay shareable.
+ * A launch is small when it has fewer than small_tasks_per_worker nodes per
+ * worker; small launches use the *_small settings, others the *_large ones.
+ *   chunk_shift_*:  see above (0..63)
  *   help_after_*:   chunks a split search must have handed out before idle
  *                   workers join it, >= 1
  *   max_workers:    cap on the persistent grid (0: the occupancy limit)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
- * restores the defaults; RS_ERR_INVALID_ARG for a zero count.
+ * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
  */
 typedef struct {
-  uint32_t rounds_split_small, help_after_small;
-  uint32_t rounds_split_large, help_after_large;
+  uint32_t chunk_shift_small, help_after_small;
+  uint32_t chunk_shift_large, help_after_large;
   uint32_t small_tasks_per_worker;
   uint32_t max_workers;
 } rs_schedule;

@@ -1,16 +1,17 @@
 """Autotuner of the seed-search schedule (rs_set_schedule).
 
 The schedule decides how the persistent search kernel hands out attempts --
-chunk length of a split search, how soon idle workers join a long search,
-grid size -- and never what it finds: every schedule yields the same
-structure.  Small launches (few nodes per worker, e.g. one small request)
-are latency bound and want short chunks that idle workers share early;
-large launches are throughput bound and want long chunks with little
-scheduling traffic.
+the chunk length of a split search relative to its expected length, how
+soon idle workers join a long search, the grid size -- and never what it
+finds: every schedule yields the same structure.  Small launches (few nodes
+per worker, e.g. one small request) are latency bound and want short chunks
+that idle workers share early; large launches are throughput bound and want
+few claims (little scheduling traffic) as long as that costs no time.
 
 ``tune()`` times the search kernel (HIP events around the launch, reported
 in the build statistics) on synthetic key sets for every candidate setting
-of each launch class and returns the fastest schedule; ``python -m
+of each launch class and keeps, among the settings within ``tol`` of the
+fastest, the one with the longest chunks; ``python -m
 paper_2212_09562_amd.autotune`` prints it as JSON, and ``apply()`` installs
 a schedule for the process.  The library's built-in defaults are this
 tuner's result on an MI355X.
@@ -26,8 +27,8 @@ from . import keygen, recsplit
 # (n, leaf size, bucket size) of the key sets each launch class is timed on
 SMALL_SETS = [(10_000, 12, 1000), (30_000, 12, 1000), (20_000, 16, 2000)]
 LARGE_SETS = [(1_000_000, 12, 1000), (10_000_000, 12, 1000), (1_000_000, 8, 100),
-              (300_000, 16, 2000)]
-ROUNDS = (1, 2, 4, 8, 16, 32)
+              (1_000_000, 16, 2000)]
+SHIFTS = (8, 10, 12, 14, 16, 63)
 HELP_AFTER = (1, 2, 4)
 
 
@@ -43,9 +44,9 @@ def _time_sets(sets, keys, reps):
     return total
 
 
-def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, rounds=ROUNDS, help_after=HELP_AFTER,
-         reps=3, seed=11, log=None):
-    """Fastest (rounds_split, help_after) per launch class; returns the schedule
+def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, shifts=SHIFTS, help_after=HELP_AFTER,
+         reps=3, seed=11, tol=0.01, log=None):
+    """Fastest (chunk_shift, help_after) per launch class; returns the schedule
     dict and the timing table."""
     import torch
 
@@ -63,18 +64,20 @@ def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, rounds=ROUNDS, help_after
                 "small_tasks_per_worker": 1}
             _time_sets(sets, ks, 1)  # warm-up
             results = []
-            for r in rounds:
+            for r in shifts:
                 for h in help_after:
-                    recsplit.set_schedule(base, **force, **{f"rounds_split_{cls}": r,
+                    recsplit.set_schedule(base, **force, **{f"chunk_shift_{cls}": r,
                                                             f"help_after_{cls}": h})
                     t = _time_sets(sets, ks, reps)
                     results.append((t, r, h))
                     if log:
-                        log(f"{cls} rounds_split={r} help_after={h}: {t:.3f} ms")
+                        log(f"{cls} chunk_shift={r} help_after={h}: {t:.3f} ms")
             results.sort()
-            table[cls] = [{"ms": t, "rounds_split": r, "help_after": h} for t, r, h in results]
-            best[f"rounds_split_{cls}"] = results[0][1]
-            best[f"help_after_{cls}"] = results[0][2]
+            table[cls] = [{"ms": t, "chunk_shift": r, "help_after": h} for t, r, h in results]
+            near = [x for x in results if x[0] <= results[0][0] * (1.0 + tol)]
+            _, r, h = min(near, key=lambda x: (x[1], -x[2]))
+            best[f"chunk_shift_{cls}"] = r
+            best[f"help_after_{cls}"] = h
     finally:
         recsplit.set_schedule(None)
     return best, table

@@ -93,7 +93,7 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
-constexpr rs_schedule kDefaultSchedule = {1, 1, 1, 2, 8, 0};  // autotune.py on an MI355X
+constexpr rs_schedule kDefaultSchedule = {63, 2, 16, 4, 8, 0};  // autotune.py on an MI355X
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
@@ -659,7 +659,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     P.stage_cap = maxm;
     // chunking of split searches (the result does not depend on it)
     const bool small = total < (uint64_t)sched.small_tasks_per_worker * workers;
-    P.rounds_split = small ? sched.rounds_split_small : sched.rounds_split_large;
+    P.chunk_shift = small ? sched.chunk_shift_small : sched.chunk_shift_large;
     P.help_after = small ? sched.help_after_small : sched.help_after_large;
     P.cap_shift = 10;
     P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
@@ -949,7 +949,7 @@ void rs_free(rs_mphf* f) { mphf_release(f); }
 
 int rs_set_schedule(const rs_schedule* sc) {
   rs_schedule v = sc ? *sc : kDefaultSchedule;
-  if (!v.rounds_split_small || !v.help_after_small || !v.rounds_split_large ||
+  if (v.chunk_shift_small > 63 || !v.help_after_small || v.chunk_shift_large > 63 ||
       !v.help_after_large || !v.small_tasks_per_worker)
     return RS_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lock(g_schedule_mu);

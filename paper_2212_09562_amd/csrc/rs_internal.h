@@ -174,7 +174,7 @@ struct SearchParams {
   const uint64_t* start;  // starting seed per depth
   uint32_t workers;
   uint32_t stage_cap;  // keys staged in LDS per worker
-  uint32_t rounds_split;  // rounds of 256 attempts per claimed split chunk
+  uint32_t chunk_shift;   // a split chunk: 2^clamp(tau - chunk_shift, 0, 8) rounds of 256
   uint32_t help_after;    // chunks a split search hands out before helpers join
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)

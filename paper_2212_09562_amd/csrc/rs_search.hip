@@ -461,7 +461,11 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
     __syncthreads();
     return;
   }
-  const uint32_t rounds = c.kind == kBinary ? 1u : P.rounds_split;
+  // long searches in long chunks (few claims), short ones in short chunks
+  // (shared early); the Rice parameter is about log2 of the expected attempts
+  const uint32_t tau = uni((uint32_t)J.tau[c.m]);
+  const uint32_t e = tau > P.chunk_shift ? (tau - P.chunk_shift < 8 ? tau - P.chunk_shift : 8) : 0;
+  const uint32_t rounds = c.kind == kBinary ? 1u : (1u << e);
   const uint64_t per_chunk = (uint64_t)rounds * kWG;
   TaskState* st = P.states + slot;
   for (;;) {

@@ -90,8 +90,8 @@ _lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
 
 
 class Schedule(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_uint32) for k in ("rounds_split_small", "help_after_small",
-                                                "rounds_split_large", "help_after_large",
+    _fields_ = [(k, ctypes.c_uint32) for k in ("chunk_shift_small", "help_after_small",
+                                                "chunk_shift_large", "help_after_large",
                                                 "small_tasks_per_worker", "max_workers")]
 
     def as_dict(self):

@@ -96,9 +96,9 @@ def test_device_keys_and_determinism():
     k16 = keys[:2500]
     want16 = oracle.build(k16, 16, 2000, True)[0]
     try:
-        for sched in ({"rounds_split_small": 3, "rounds_split_large": 3, "help_after_small": 1,
+        for sched in ({"chunk_shift_small": 3, "chunk_shift_large": 3, "help_after_small": 1,
                        "help_after_large": 1, "max_workers": 37},
-                      {"rounds_split_small": 1, "rounds_split_large": 64, "help_after_small": 5,
+                      {"chunk_shift_small": 0, "chunk_shift_large": 63, "help_after_small": 5,
                        "help_after_large": 1, "small_tasks_per_worker": 1000}):
             rs().set_schedule(None)
             rs().set_schedule(**sched)

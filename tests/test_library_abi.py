@@ -101,10 +101,13 @@ def test_schedule_defaults_and_validation():
     from paper_2212_09562_amd import recsplit
 
     d = recsplit.set_schedule(None)
-    assert all(d[k] >= 1 for k in d if k != "max_workers")
+    assert d["help_after_small"] >= 1 and d["help_after_large"] >= 1
     with pytest.raises(recsplit.RecSplitError) as e:
-        recsplit.set_schedule(rounds_split_large=0)
+        recsplit.set_schedule(help_after_large=0)
+    assert e.value.code == -1
+    with pytest.raises(recsplit.RecSplitError) as e:
+        recsplit.set_schedule(chunk_shift_large=64)
     assert e.value.code == -1
     assert recsplit.get_schedule() == d
-    assert recsplit.set_schedule(rounds_split_large=7)["rounds_split_large"] == 7
+    assert recsplit.set_schedule(chunk_shift_large=7)["chunk_shift_large"] == 7
     assert recsplit.set_schedule(None) == d
