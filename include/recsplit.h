@@ -130,9 +130,11 @@ typedef struct {
   uint64_t hbm_budget_bytes;    /* device pool size, >= 1 MiB */
   uint32_t max_slots;           /* concurrent builds, 1..64 */
   uint32_t max_jobs_per_launch; /* requests per search launch, >= 1 */
-  uint32_t reserve_per_cu;      /* search workgroups per compute unit each launch leaves
-                                   free, so a build admitted while another runs starts
-                                   at once (0: every launch takes the whole device) */
+  uint32_t reserve_per_cu;      /* search workgroups per compute unit that launches
+                                   leave free (0: none); large launches (2^20 keys or
+                                   more) then run one at a time and a small launch
+                                   made while one runs uses only the reserve, so small
+                                   requests do not wait behind large ones */
 } rs_server_config;
 
 typedef struct {

@@ -25,6 +25,10 @@ using namespace rs;
 
 namespace {
 
+// A launch of at least this many keys counts as large (its search holds the
+// whole device for milliseconds).
+constexpr uint64_t kLargeLaunchKeys = 1ull << 20;
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -96,7 +100,10 @@ struct rs_server {
   uint64_t next_ticket = 1;
   bool stopping = false;
   uint32_t workers_max = 0;
-  uint32_t workers_cap = 0;  // search grid of each launch
+  uint32_t workers_cap = 0;      // search grid of a launch: the device minus the reserve
+  uint32_t reserve_workers = 0;  // the reserve (reserve_per_cu workers on every CU)
+  bool large_running = false;
+  std::condition_variable cv_large;
   rs_server_stats st{};
   size_t in_use = 0;
   size_t usable = 0;  // pool bytes in whole regions
@@ -168,11 +175,33 @@ void slot_loop(rs_server* S, uint32_t slot) {
         S->cv_work.wait(lock);
       }
     }
-    int rc = build_jobs(c, plan, S->pool + off, bytes, S->workers_cap);
+    // Device sharing.  A large launch holds the device for a long time, so
+    // large launches run one at a time, each leaving the reserve free; a
+    // small launch that starts while a large one runs is sized to the
+    // reserve, so it finishes without waiting for the large one.
+    uint64_t keys = 0;
+    for (const JobPlan& p : plan) keys += p.n;
+    const bool large = keys >= kLargeLaunchKeys;
+    uint32_t cap = S->workers_cap;
+    {
+      std::unique_lock<std::mutex> lock(S->mu);
+      if (large) {
+        S->cv_large.wait(lock, [&] { return !S->large_running || S->stopping; });
+        S->large_running = true;
+      } else if (S->large_running && S->reserve_workers) {
+        cap = S->reserve_workers;
+      }
+    }
+    int rc = build_jobs(c, plan, S->pool + off, bytes, cap);
     if (rc) {
       (void)hipStreamSynchronize(c.s);
       (void)hipGetLastError();
     }
+    if (large) {
+      std::lock_guard<std::mutex> lock(S->mu);
+      S->large_running = false;
+    }
+    if (large) S->cv_large.notify_all();
     {
       std::lock_guard<std::mutex> lock(S->mu);
       const double t = now_s();
@@ -220,6 +249,7 @@ int rs_server_create(const rs_server_config* cfg, rs_server** out) {
     const uint64_t cus = (uint64_t)S->dev->cus;
     const uint64_t keep = (uint64_t)cfg->reserve_per_cu * cus;
     S->workers_cap = keep + cus <= S->workers_max ? (uint32_t)(S->workers_max - keep) : (uint32_t)cus;
+    S->reserve_workers = (uint32_t)(S->workers_max - S->workers_cap);
   }
   if (hipMalloc(reinterpret_cast<void**>(&S->pool), cfg->hbm_budget_bytes) != hipSuccess) {
     delete S;
@@ -302,6 +332,7 @@ void rs_server_destroy(rs_server* S) {
     S->stopping = true;
   }
   S->cv_work.notify_all();
+  S->cv_large.notify_all();
   for (std::thread& t : S->threads) t.join();
   for (Context* c : S->ctx) {
     context_destroy(*c);
