@@ -336,6 +336,10 @@ def main():
         "valu_rates": rates,
     }
     del dev
+    # the same build from host memory: the rate including the PCIe copy of the keys
+    t0 = time.perf_counter()
+    recsplit.build(keys, l, b, rot).free()
+    out["host_keys_keys_per_s"] = n / (time.perf_counter() - t0)
     if not args.headline_only:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         out["batched"] = run_batched(recsplit, keygen, torch, max(1, args.steps), 1)

@@ -218,11 +218,20 @@ __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const
     ns += __shfl_xor(ns, d);
     nl += __shfl_xor(nl, d);
   }
-  if ((threadIdx.x & 63) == 0 && (ns | nl)) {
-    atomicAdd(&info->evals_split, es);
-    atomicAdd(&info->evals_leaf, el);
-    atomicAdd(&info->splits, ns);
-    atomicAdd(&info->leaves, nl);
+  __shared__ uint64_t part[4][4];
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[w][0] = es;
+    part[w][1] = el;
+    part[w][2] = ns;
+    part[w][3] = nl;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const uint64_t v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                       part[3][threadIdx.x];
+    uint64_t* dst[4] = {&info->evals_split, &info->evals_leaf, &info->splits, &info->leaves};
+    if (v) atomicAdd(dst[threadIdx.x], v);
   }
 }
 
@@ -332,7 +341,7 @@ hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s) {
 hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, uint32_t l,
                        uint32_t rotation, JobInfo* info, hipStream_t s) {
   if (!n) return hipSuccess;
-  k_work_counts<<<grid_for(n, 256, 2048), 256, 0, s>>>(vals, msz, n, l, rotation, info);
+  k_work_counts<<<grid_for(n, 256 * 8, 512), 256, 0, s>>>(vals, msz, n, l, rotation, info);
   return hipGetLastError();
 }
 
