@@ -180,13 +180,16 @@ void rs_server_destroy(rs_server *s);
  *   chunk_shift_*:  see above (0..63)
  *   help_after_*:   chunks a split search must have handed out before idle
  *                   workers join it, >= 1
+ *   inline_leaf_tau_*: a leaf child whose Rice parameter is below this is
+ *                   searched by the worker that split its parent, right after
+ *                   the split, instead of going through the queue (0: never)
  *   max_workers:    cap on the persistent grid (0: the occupancy limit)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
  * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
  */
 typedef struct {
-  uint32_t chunk_shift_small, help_after_small;
-  uint32_t chunk_shift_large, help_after_large;
+  uint32_t chunk_shift_small, help_after_small, inline_leaf_tau_small;
+  uint32_t chunk_shift_large, help_after_large, inline_leaf_tau_large;
   uint32_t small_tasks_per_worker;
   uint32_t max_workers;
 } rs_schedule;

@@ -10,8 +10,10 @@ few claims (little scheduling traffic) as long as that costs no time.
 
 ``tune()`` times the search kernel (HIP events around the launch, reported
 in the build statistics) on synthetic key sets for every candidate setting
-of each launch class and keeps, among the settings within ``tol`` of the
-fastest, the one with the longest chunks; ``python -m
+of each launch class; the cost of a setting is the sum over the sets of its
+time relative to the defaults' (every set weighs the same), and among the
+settings within ``tol`` of the cheapest it keeps the one with the longest
+chunks; ``python -m
 paper_2212_09562_amd.autotune`` prints it as JSON, and ``apply()`` installs
 a schedule for the process.  The library's built-in defaults are this
 tuner's result on an MI355X.
@@ -27,27 +29,33 @@ from . import keygen, recsplit
 # (n, leaf size, bucket size) of the key sets each launch class is timed on
 SMALL_SETS = [(10_000, 12, 1000), (30_000, 12, 1000), (20_000, 16, 2000)]
 LARGE_SETS = [(1_000_000, 12, 1000), (10_000_000, 12, 1000), (1_000_000, 8, 100),
-              (1_000_000, 16, 2000)]
-SHIFTS = (8, 10, 12, 14, 16, 63)
+              (1_000_000, 16, 2000), (3_000_000, 16, 2000)]
+SHIFTS = (8, 10, 12, 13, 14, 15, 16, 18, 63)
 HELP_AFTER = (1, 2, 4)
+INLINE_TAU = (0, 10, 13, 16, 20)
 
 
-def _time_sets(sets, keys, reps):
-    total = 0.0
+def _time_sets(sets, keys, reps, ref=None):
+    """Median search time of each set; with ``ref`` (times of a reference
+    schedule) the sum of the ratios, so every set weighs the same."""
+    times = []
     for (n, l, b), k in zip(sets, keys):
         ms = []
         for _ in range(reps):
             f = recsplit.build(k, l, b, True)
             ms.append(f.stats()["ms_search"])
             f.free()
-        total += statistics.median(ms)
-    return total
+        times.append(statistics.median(ms))
+    if ref is None:
+        return times
+    return sum(t / r for t, r in zip(times, ref))
 
 
 def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, shifts=SHIFTS, help_after=HELP_AFTER,
-         reps=3, seed=11, tol=0.01, log=None):
-    """Fastest (chunk_shift, help_after) per launch class; returns the schedule
-    dict and the timing table."""
+         inline_tau=INLINE_TAU, reps=3, seed=11, tol=0.01, log=None):
+    """Per launch class: the fastest (chunk_shift, help_after), then the
+    fastest inline_leaf_tau with those; returns the schedule dict and the
+    timing table."""
     import torch
 
     base = recsplit.set_schedule(None)
@@ -63,21 +71,37 @@ def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, shifts=SHIFTS, help_after
             force = {"small_tasks_per_worker": 1 << 30} if cls == "small" else {
                 "small_tasks_per_worker": 1}
             _time_sets(sets, ks, 1)  # warm-up
+            recsplit.set_schedule(base, **force)
+            ref = _time_sets(sets, ks, reps)
+            if log:
+                log(f"{cls} reference (defaults): " + ", ".join(f"{t:.3f}" for t in ref) + " ms")
             results = []
             for r in shifts:
                 for h in help_after:
                     recsplit.set_schedule(base, **force, **{f"chunk_shift_{cls}": r,
                                                             f"help_after_{cls}": h})
-                    t = _time_sets(sets, ks, reps)
+                    t = _time_sets(sets, ks, reps, ref)
                     results.append((t, r, h))
                     if log:
-                        log(f"{cls} chunk_shift={r} help_after={h}: {t:.3f} ms")
+                        log(f"{cls} chunk_shift={r} help_after={h}: {t:.4f}")
             results.sort()
-            table[cls] = [{"ms": t, "chunk_shift": r, "help_after": h} for t, r, h in results]
+            table[cls] = [{"cost": t, "chunk_shift": r, "help_after": h} for t, r, h in results]
             near = [x for x in results if x[0] <= results[0][0] * (1.0 + tol)]
             _, r, h = min(near, key=lambda x: (x[1], -x[2]))
             best[f"chunk_shift_{cls}"] = r
             best[f"help_after_{cls}"] = h
+            # then the leaf inlining threshold with those
+            results = []
+            for it in inline_tau:
+                recsplit.set_schedule(best, **force, **{f"inline_leaf_tau_{cls}": it})
+                t = _time_sets(sets, ks, reps, ref)
+                results.append((t, it))
+                if log:
+                    log(f"{cls} inline_leaf_tau={it}: {t:.4f}")
+            results.sort()
+            table[cls + "_inline"] = [{"cost": t, "inline_leaf_tau": it} for t, it in results]
+            table[cls + "_reference_ms"] = ref
+            best[f"inline_leaf_tau_{cls}"] = results[0][1]
     finally:
         recsplit.set_schedule(None)
     return best, table

@@ -93,7 +93,7 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
-constexpr rs_schedule kDefaultSchedule = {63, 2, 16, 4, 8, 0};  // autotune.py on an MI355X
+constexpr rs_schedule kDefaultSchedule = {63, 2, 10, 16, 4, 13, 8, 0};
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
@@ -661,6 +661,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     const bool small = total < (uint64_t)sched.small_tasks_per_worker * workers;
     P.chunk_shift = small ? sched.chunk_shift_small : sched.chunk_shift_large;
     P.help_after = small ? sched.help_after_small : sched.help_after_large;
+    P.inline_leaf_tau = small ? sched.inline_leaf_tau_small : sched.inline_leaf_tau_large;
     P.cap_shift = 10;
     P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
     HIPCHECK(hipEventRecord(c.ev[3], s));

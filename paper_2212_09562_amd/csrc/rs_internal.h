@@ -176,6 +176,7 @@ struct SearchParams {
   uint32_t stage_cap;  // keys staged in LDS per worker
   uint32_t chunk_shift;   // a split chunk: 2^clamp(tau - chunk_shift, 0, 8) rounds of 256
   uint32_t help_after;    // chunks a split search hands out before helpers join
+  uint32_t inline_leaf_tau;  // leaf children with tau below this skip the queue
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
 };

@@ -315,11 +315,21 @@ __device__ void stage_keys(const Task& t, const JobDev& J, const Node& c, uint64
 // ping-pong array (stable within each child), then queue the children.  Run
 // by wave 0; lane 0 queues.  The queue slots are reserved with one atomic
 // before the keys move, and one release fence publishes keys and records.
+// A leaf child of a split whose Rice parameter is below the launch's
+// inline_leaf_tau is searched by the worker that split its parent, right
+// after the split, instead of going through the queue.
+__device__ __forceinline__ bool queued_child(const SearchParams& P, const JobDev& J, uint32_t l,
+                                             uint32_t sz) {
+  return sz >= 2 && (sz > l || (uint32_t)J.tau[sz] >= P.inline_leaf_tau);
+}
+
 __device__ void finalize_split(const SearchParams& P, const Task& t, const JobDev& J,
                                const Node& c, uint64_t s) {
   const uint32_t lane = lane_id();
-  uint32_t nkids = 0;  // children that are stored nodes
-  for (uint32_t j = 0; j < c.k; ++j) nkids += (j + 1 < c.k ? c.unit : c.last) >= 2 ? 1u : 0u;
+  const uint32_t l = uni(J.l);
+  uint32_t nkids = 0;  // children that go through the queue
+  for (uint32_t j = 0; j < c.k; ++j)
+    nkids += queued_child(P, J, l, j + 1 < c.k ? c.unit : c.last) ? 1u : 0u;
   uint64_t base = 0;
   if (lane == 0 && nkids)
     base = __hip_atomic_fetch_add(&P.ctl->tail, (uint64_t)nkids, __ATOMIC_RELAXED,
@@ -361,7 +371,7 @@ __device__ void finalize_split(const SearchParams& P, const Task& t, const JobDe
       uint64_t child_node = t.node + 1, slot = base;
       for (uint32_t j = 0; j < c.k; ++j) {
         const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
-        if (sz >= 2) {
+        if (queued_child(P, J, l, sz)) {
           Task ct;
           ct.key_off = t.key_off + (uint64_t)j * c.unit;
           ct.node = child_node;
@@ -424,6 +434,31 @@ struct Shared {
   int32_t pick;
 };
 
+// A leaf is short and there are many: one worker searches it alone, as one
+// chunk without a bound on its rounds, with no global traffic until the value
+// is known.  Nobody joins a leaf (its state is never claimed).
+__device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
+                         const JobDev& J, uint64_t slot) {
+  const uint32_t tid = threadIdx.x;
+  Node c = make_node(t, J, P.start, P.cap_shift);
+  stage_keys(t, J, c, s_keys, &sh.na);
+  if (tid == 0) sh.best = kInf;
+  __syncthreads();
+  c.na = uni(sh.na);
+  const uint64_t max_rounds = c.cap / kWG + 1;
+  eval_chunk(s_keys, c, 0, max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu,
+             &sh.best);
+  __syncthreads();
+  const uint64_t v = sh.best;
+  if (v == kInf) {
+    if (tid == 0 && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
+      record_failure(P.ctl, t, slot, P.states + (slot < P.ctl->total ? slot : 0), 0);
+  } else {
+    finalize_leaf(P, t, J, c, v);
+  }
+  __syncthreads();
+}
+
 // Work on task `slot` until this worker's claim is refused.  my_q (thread 0
 // only) is the queue slot this worker has reserved; a helper leaves as soon
 // as that slot is ready.
@@ -437,30 +472,13 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   t.depth = (uint16_t)uni(t.depth);
   t.job = (uint16_t)uni(t.job);
   const JobDev& J = P.jobs[t.job];
+  if (t.m <= uni(J.l)) {
+    run_leaf(P, sh, s_keys, t, J, slot);
+    return;
+  }
   Node c = make_node(t, J, P.start, P.cap_shift);
   stage_keys(t, J, c, s_keys, &sh.na);
   __syncthreads();
-  if (c.kind == kLeaf) c.na = uni(sh.na);
-  if (c.kind == kLeaf) {
-    // A leaf is short and there are many: its owner searches it alone, as one
-    // chunk without a bound on its rounds, with no global traffic until the
-    // value is known.  Nobody joins a leaf (its state is never claimed).
-    if (tid == 0) sh.best = kInf;
-    __syncthreads();
-    const uint64_t max_rounds = c.cap / kWG + 1;
-    eval_chunk(s_keys, c, 0, max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu,
-               &sh.best);
-    __syncthreads();
-    const uint64_t v = sh.best;
-    if (v == kInf) {
-      if (tid == 0 && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
-        record_failure(P.ctl, t, slot, P.states + slot, 0);
-    } else {
-      finalize_leaf(P, t, J, c, v);
-    }
-    __syncthreads();
-    return;
-  }
   // long searches in long chunks (few claims), short ones in short chunks
   // (shared early); the Rice parameter is about log2 of the expected attempts
   const uint32_t tau = uni((uint32_t)J.tau[c.m]);
@@ -532,6 +550,22 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       const uint64_t v = sh.fin_value;
       if (tid < 64) finalize_split(P, t, J, c, v);
       __syncthreads();
+      // the leaf children kept out of the queue, searched here in order
+      const uint32_t l = uni(J.l);
+      uint64_t child_node = t.node + 1;
+      for (uint32_t j = 0; j < c.k; ++j) {
+        const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
+        if (sz >= 2 && !queued_child(P, J, l, sz)) {
+          Task ct;
+          ct.key_off = t.key_off + (uint64_t)j * c.unit;
+          ct.node = child_node;
+          ct.m = sz;
+          ct.depth = (uint16_t)(t.depth + 1);
+          ct.job = t.job;
+          run_leaf(P, sh, s_keys, ct, J, kNoSlot);
+        }
+        child_node += uni(J.nodecnt[sz]);
+      }
       return;
     }
     if (chunk == kStop) return;
@@ -568,7 +602,9 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
           act = kActOwn;
           sh.arg = my_q;
           my_q = kNoSlot;
-        } else if (my_q == kExhausted && ld_relaxed(&P.ctl->finished) >= total) {
+        } else if (ld_relaxed(&P.ctl->finished) >= total) {
+          // every node is final (slots a worker still holds may never be
+          // filled: inline leaves take none)
           act = kActExit;
         } else if (ld_relaxed(&P.ctl->long_tasks) != 0) {
           act = kActScan;

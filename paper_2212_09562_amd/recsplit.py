@@ -91,7 +91,8 @@ _lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
 
 class Schedule(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in ("chunk_shift_small", "help_after_small",
-                                                "chunk_shift_large", "help_after_large",
+                                                "inline_leaf_tau_small", "chunk_shift_large",
+                                                "help_after_large", "inline_leaf_tau_large",
                                                 "small_tasks_per_worker", "max_workers")]
 
     def as_dict(self):

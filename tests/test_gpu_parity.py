@@ -97,9 +97,12 @@ def test_device_keys_and_determinism():
     want16 = oracle.build(k16, 16, 2000, True)[0]
     try:
         for sched in ({"chunk_shift_small": 3, "chunk_shift_large": 3, "help_after_small": 1,
-                       "help_after_large": 1, "max_workers": 37},
+                       "help_after_large": 1, "max_workers": 37, "inline_leaf_tau_small": 0,
+                       "inline_leaf_tau_large": 0},
                       {"chunk_shift_small": 0, "chunk_shift_large": 63, "help_after_small": 5,
-                       "help_after_large": 1, "small_tasks_per_worker": 1000}):
+                       "help_after_large": 1, "small_tasks_per_worker": 1000,
+                       "inline_leaf_tau_small": 64, "inline_leaf_tau_large": 64},
+                      {"small_tasks_per_worker": 1, "inline_leaf_tau_large": 9}):
             rs().set_schedule(None)
             rs().set_schedule(**sched)
             assert rs().build(keys[perm], 8, 100, True).serialize() == want
