@@ -178,16 +178,18 @@ void slot_loop(rs_server* S, uint32_t slot) {
     // Device sharing.  A large launch holds the device for a long time, so
     // large launches run one at a time, each leaving the reserve free; a
     // small launch that starts while a large one runs is sized to the
-    // reserve, so it finishes without waiting for the large one.
+    // reserve, so it finishes without waiting for the large one; otherwise a
+    // small launch takes the whole device (it ends soon).
     uint64_t keys = 0;
     for (const JobPlan& p : plan) keys += p.n;
     const bool large = keys >= kLargeLaunchKeys;
-    uint32_t cap = S->workers_cap;
+    uint32_t cap = 0;
     {
       std::unique_lock<std::mutex> lock(S->mu);
       if (large) {
         S->cv_large.wait(lock, [&] { return !S->large_running || S->stopping; });
         S->large_running = true;
+        cap = S->workers_cap;
       } else if (S->large_running && S->reserve_workers) {
         cap = S->reserve_workers;
       }
