@@ -88,6 +88,46 @@ def cpu_baseline(keys, l, b, buckets):
             "seconds": dt, "useful_evals_per_s": (st["evals_split"] + st["evals_leaf"]) / dt}
 
 
+def run_query(f, dev, torch, reps=5):
+    """Evaluation of the built function on all its keys (device resident) with
+    the library's query kernel: ranks per second."""
+    out = torch.empty(dev.shape[0], dtype=torch.int64, device=dev.device)
+    f.query(dev, out)  # first call makes the structure's device copy
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f.query(dev, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"keys_per_s": dev.shape[0] / dt, "ns_per_key": dt * 1e9 / dev.shape[0],
+            "ms_per_call": dt * 1e3, "keys": int(dev.shape[0])}
+
+
+def run_sweep(recsplit, keygen, torch, n=1_000_000, leaf_sizes=range(5, 17),
+              bucket_sizes=(5, 50, 500, 2000)):
+    """Construction time and space over leaf size, bucket size and leaf
+    method (brute force, rotation fitting) on one set of n keys."""
+    keys = keygen.fingerprints_torch(n, 21, "cuda")
+    torch.cuda.synchronize()
+    recsplit.build(keys, 8, 100, True).free()
+    rows = []
+    for rot in (False, True):
+        for l in leaf_sizes:
+            for b in bucket_sizes:
+                t0 = time.perf_counter()
+                f = recsplit.build(keys, l, b, rot)
+                dt = time.perf_counter() - t0
+                st = f.stats()
+                f.free()
+                ev = st["useful_evals_split"] + st["useful_evals_leaf"]
+                rows.append({"leaf_method": "rotation" if rot else "brute", "l": l, "b": b,
+                             "ns_per_key": dt * 1e9 / n, "bits_per_key": st["bytes"] * 8 / n,
+                             "ms_search": st["ms_search"], "evals_per_key": ev / n,
+                             "hash_evals_per_s": ev / (st["ms_search"] * 1e-3)})
+                print(f"[sweep] {rows[-1]}", file=sys.stderr, flush=True)
+    return {"n": n, "rows": rows}
+
+
 def _search_roofline(evals, ms_search):
     evals_per_s = evals / (ms_search * 1e-3)
     achieved = evals_per_s * OPS_PER_EVAL / 1e12
@@ -262,6 +302,8 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--per-launch", type=int, default=8)
     ap.add_argument("--reserve-per-cu", type=int, default=1)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead: leaf size x bucket size x leaf method sweep on 10^6 keys")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the construction is not "
@@ -271,6 +313,10 @@ def main():
     import torch
 
     from paper_2212_09562_amd import keygen, recsplit
+
+    if args.sweep:
+        print(json.dumps({"sweep": run_sweep(recsplit, keygen, torch)}), flush=True)
+        return
 
     l, b, rot = WORKLOAD["leaf_size"], WORKLOAD["bucket_size"], WORKLOAD["rotation"]
     n = args.n
@@ -290,14 +336,18 @@ def main():
         recsplit.build(dev, l, b, rot).free()
     torch.cuda.synchronize()
     stats = []
+    f = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        if f is not None:
+            f.free()
         f = recsplit.build(dev, l, b, rot)
         stats.append(f.stats())
-        f.free()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     secs = t1 - t0
+    query = run_query(f, dev, torch)
+    f.free()
     st = stats[-1]
     evals = st["useful_evals_split"] + st["useful_evals_leaf"]
     ms_search = sum(s["ms_search"] for s in stats) / len(stats)
@@ -331,6 +381,7 @@ def main():
                      "sustained_hash_loop_evals_per_s": rates["hash_evals_sustained"],
                      "frac_of_sustained_hash_loop": evals_per_s / rates["hash_evals_sustained"]},
         "bits_per_key": st["bytes"] * 8 / n,
+        "query": query,
         "stage_ms": {k: sum(s[k] for s in stats) / len(stats)
                      for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},
         "valu_rates": rates,

@@ -487,6 +487,10 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   const uint64_t per_chunk = (uint64_t)rounds * kWG;
   TaskState* st = P.states + slot;
   for (;;) {
+    // every wave has read the previous round's sh.fin and sh.chunk before
+    // thread 0 overwrites them (without this a slow wave could read the next
+    // round's decision and leave the workgroup's barriers out of step)
+    __syncthreads();
     if (tid == 0) {
       sh.fin = 0;
       sh.best = kInf;

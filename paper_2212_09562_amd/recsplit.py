@@ -178,7 +178,7 @@ class MPHF:
 
     def free(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.rs_free(h)
             self._h = ctypes.c_void_p(0)
 
@@ -287,7 +287,7 @@ class Server:
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.rs_server_destroy(h)
             self._h = ctypes.c_void_p(0)
             self._keep.clear()

@@ -159,6 +159,14 @@ def test_largest_buckets():
     _check_parity(keygen.fingerprints(12000, 15), 8, 4096, True)
 
 
+@pytest.mark.parametrize("n,l,b,rot", [(2000, 18, 50, True), (150, 18, 50, False),
+                                       (600, 20, 100, True), (30, 24, 30, True)])
+def test_leaf_sizes_above_16(n, l, b, rot):
+    """The space-efficient leaf sizes of Sec. 6 (l = 18, 20, 24) on sets the
+    oracle can afford; l = 24 leaves need values above 2^32."""
+    _check_parity(keygen.fingerprints(n, 910 + l + n), l, b, rot)
+
+
 def test_leaf16_two_buckets():
     _case("l=16 b=2000 n=4000 (two buckets)")
     _check_parity(keygen.fingerprints(4000, 16), 16, 2000, True)
