@@ -34,12 +34,14 @@ METRIC = "MPHF construction keys/sec at ℓ=16,b=2000 (bit-exact) + % int-ALU ro
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: full-rate 32-bit VALU lane-operations per second
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# One hash evaluation plus its position/count update, as issued per key and
-# lane by the search kernel's inner loop (counted from the gfx950 ISA):
-# 64-bit add of the identifier, two 64-bit xorshifts (shift + 2 xor each),
-# two 64x64 multiplies (3 multiply-class + 1 add3 each; the second keeps only
-# the high word), the final xorshift of the top word (2), the multiply-high
-# reduction to a position or child (1) and the bit/counter update (1).
+# One hash evaluation plus its position update, as issued per key and lane by
+# the search kernel's inner loop (counted from the gfx950 ISA): 64-bit add of
+# the identifier, two 64-bit xorshifts (shift + 2 xor each), two 64x64
+# multiplies (3 multiply-class + 1 add3 each; the second keeps only the high
+# word), the final xorshift of the top word (2), the multiply-high reduction
+# to a position or child (1) and the bit update (1).  A split attempt with
+# packed child counters needs one more (the field offset); 19 is used for
+# every evaluation, a lower bound on the algorithmic work.
 OPS_PER_EVAL = 19
 INSTRUCTION_MIX = {"lshl_add_u64": 1, "lshrrev_b64": 2, "xor_b32": 5, "mad_u64_u32": 1,
                    "mul_lo_u32": 4, "mul_hi_u32": 2, "add3_u32": 2, "add_u32": 2}
