@@ -402,24 +402,31 @@ __device__ void finalize_leaf(const SearchParams& P, const Task& t, const JobDev
   }
 }
 
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// The claim word of a task (TaskState::np): chunks in flight in the low 32
+// bits, the next chunk index in bits 32..62, and bit 63 set once some chunk
+// has produced a value.  Chunks are claimed in increasing order, so a chunk
+// claimed after that bit is set lies wholly above the value and is dropped
+// unevaluated; one atomic both drops an evaluated chunk and claims the next.
+constexpr uint64_t kFound = 1ull << 63;
+constexpr uint64_t kClaim = 1ull << 32;
+__device__ __forceinline__ uint64_t chunk_index(uint64_t np) { return (np >> 32) & 0x7FFFFFFFull; }
+
 // Drop one in-flight chunk of task st; returns true for the one caller that
-// must finalize (the task has a value and nothing is in flight any more).
-// Relaxed agent-scope atomics: the value and the counters share one cache line
-// of the task state, every such atomic is performed at the device coherence
-// point, and a caller that published a value waited for that atomic to
-// complete before dropping its chunk, so whoever sees the count reach zero
-// also sees the value.
+// must finalize (a value is known and nothing is in flight any more).
+// Relaxed agent-scope atomics on one cache line of the task state, performed
+// at the device coherence point; a caller that found a value waited for its
+// atomicMin and for the found bit before dropping its chunk, so whoever sees
+// the count reach zero with the bit set also sees the value.
 __device__ __forceinline__ bool release_chunk(TaskState* st) {
   const uint64_t old =
       __hip_atomic_fetch_add(&st->np, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if ((old & 0xFFFFFFFFull) != 1) return false;
-  if (ld_relaxed(&st->best) == kInf) return false;
+  if ((old & 0xFFFFFFFFull) != 1 || !(old & kFound)) return false;
   uint32_t expected = 0;
   return __hip_atomic_compare_exchange_strong(&st->closed, &expected, 1u, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 struct Shared {
   Task task;
@@ -486,93 +493,98 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   const uint32_t rounds = c.kind == kBinary ? 1u : (1u << e);
   const uint64_t per_chunk = (uint64_t)rounds * kWG;
   TaskState* st = P.states + slot;
+  // Thread 0 turns the word returned by a claim into the chunk to evaluate,
+  // or drops the claim (value known, limit passed) and returns kStop.
+  auto decide = [&](uint64_t old) -> uint64_t {
+    const uint64_t ci = chunk_index(old);
+    if (old & kFound) {
+      sh.fin = release_chunk(st) ? 1u : 0u;
+      return kStop;
+    }
+    // every worker may hold one claimed chunk whose result is not in yet
+    if (ci * per_chunk >= c.cap + (uint64_t)P.workers * per_chunk) {
+      if (set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT))) record_failure(P.ctl, t, slot, st, ci);
+      sh.fin = release_chunk(st) ? 1u : 0u;
+      return kStop;
+    }
+    if (ci == P.help_after) {
+      // a long search: count it so idle workers look for it
+      uint32_t expected = 0;
+      if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 1u, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        __hip_atomic_fetch_add(&P.ctl->long_tasks, 1ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      wait_memory();  // counted before this chunk can be dropped
+    }
+    return ci;
+  };
+  // a helper leaves as soon as the queue slot it holds is ready
+  auto leave = [&]() {
+    return ld_relaxed(&P.ctl->error) != 0 ||
+           (!own && my_q < kExhausted && ld_relaxed(&P.ready[my_q]) != 0);
+  };
+  if (tid == 0) {
+    sh.fin = 0;
+    sh.best = kInf;
+    sh.chunk = leave() ? kStop
+                       : decide(__hip_atomic_fetch_add(&st->np, kClaim | 1ull, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+  }
   for (;;) {
-    // every wave has read the previous round's sh.fin and sh.chunk before
-    // thread 0 overwrites them (without this a slow wave could read the next
-    // round's decision and leave the workgroup's barriers out of step)
-    __syncthreads();
-    if (tid == 0) {
-      sh.fin = 0;
-      sh.best = kInf;
-      uint64_t chunk = kStop;
-      if (ld_relaxed(&P.ctl->error) != 0) {
-        chunk = kStop;
-      } else if (!own && my_q < kExhausted && ld_relaxed(&P.ready[my_q]) != 0) {
-        chunk = kStop;
-      } else {
-        const uint64_t old = __hip_atomic_fetch_add(&st->np, (1ull << 32) | 1ull,
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t ci = old >> 32;
-        const uint64_t best = ld_relaxed(&st->best);
-        const uint64_t first = ci * per_chunk;
-        // every worker may hold one claimed chunk whose result is not in yet
-        if (first >= c.cap + (uint64_t)P.workers * per_chunk) {
-          if (best == kInf && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
-            record_failure(P.ctl, t, slot, st, ci);
-          sh.fin = release_chunk(st) ? 1u : 0u;
-        } else if (best != kInf && first * c.mult >= best) {
-          sh.fin = release_chunk(st) ? 1u : 0u;
-        } else {
-          chunk = ci;
-          if (ci == P.help_after && best == kInf) {
-            // a long search: count it so idle workers look for it
-            uint32_t expected = 0;
-            if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 1u, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-              __hip_atomic_fetch_add(&P.ctl->long_tasks, 1ull, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-            wait_memory();  // counted before this chunk can be dropped
-          }
-        }
-      }
-      sh.chunk = chunk;
-    }
-    __syncthreads();
+    __syncthreads();  // thread 0's decision is visible
     const uint64_t chunk = sh.chunk;
-    if (chunk != kStop) {
-      eval_chunk(s_keys, c, chunk, rounds, &sh.best);
-      __syncthreads();
-      if (tid == 0) {
-        if (sh.best != kInf) {
-          __hip_atomic_fetch_min(&st->best, sh.best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          wait_memory();  // the value is in before the chunk is dropped
-        }
+    if (chunk == kStop) break;
+    eval_chunk(s_keys, c, chunk, rounds, &sh.best);
+    __syncthreads();  // the chunk's best is final; every thread has read the decision
+    if (tid == 0) {
+      const uint64_t v = sh.best;
+      sh.best = kInf;
+      sh.fin = 0;
+      uint64_t next = kStop;
+      if (v != kInf) {
+        __hip_atomic_fetch_min(&st->best, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_memory();  // the value is in before the found bit
+        __hip_atomic_fetch_or(&st->np, kFound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_memory();  // and the bit before the chunk is dropped
         sh.fin = release_chunk(st) ? 1u : 0u;
+      } else if (leave()) {
+        sh.fin = release_chunk(st) ? 1u : 0u;
+      } else {
+        // drop the evaluated chunk and claim the next with one atomic
+        next = decide(__hip_atomic_fetch_add(&st->np, kClaim, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
       }
-      __syncthreads();
+      sh.chunk = next;
     }
-    if (sh.fin) {
-      if (tid == 0) {
-        sh.fin_value = ld_relaxed(&st->best);
-        uint32_t expected = 1;
-        if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 2u, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-          __hip_atomic_fetch_add(&P.ctl->long_tasks, ~0ull, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __syncthreads();
-      const uint64_t v = sh.fin_value;
-      if (tid < 64) finalize_split(P, t, J, c, v);
-      __syncthreads();
-      // the leaf children kept out of the queue, searched here in order
-      const uint32_t l = uni(J.l);
-      uint64_t child_node = t.node + 1;
-      for (uint32_t j = 0; j < c.k; ++j) {
-        const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
-        if (sz >= 2 && !queued_child(P, J, l, sz)) {
-          Task ct;
-          ct.key_off = t.key_off + (uint64_t)j * c.unit;
-          ct.node = child_node;
-          ct.m = sz;
-          ct.depth = (uint16_t)(t.depth + 1);
-          ct.job = t.job;
-          run_leaf(P, sh, s_keys, ct, J, kNoSlot);
-        }
-        child_node += uni(J.nodecnt[sz]);
-      }
-      return;
+  }
+  if (!sh.fin) return;
+  if (tid == 0) {
+    sh.fin_value = ld_relaxed(&st->best);
+    uint32_t expected = 1;
+    if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 2u, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      __hip_atomic_fetch_add(&P.ctl->long_tasks, ~0ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const uint64_t v = sh.fin_value;
+  if (tid < 64) finalize_split(P, t, J, c, v);
+  __syncthreads();
+  // the leaf children kept out of the queue, searched here in order
+  const uint32_t l = uni(J.l);
+  uint64_t child_node = t.node + 1;
+  for (uint32_t j = 0; j < c.k; ++j) {
+    const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
+    if (sz >= 2 && !queued_child(P, J, l, sz)) {
+      Task ct;
+      ct.key_off = t.key_off + (uint64_t)j * c.unit;
+      ct.node = child_node;
+      ct.m = sz;
+      ct.depth = (uint16_t)(t.depth + 1);
+      ct.job = t.job;
+      run_leaf(P, sh, s_keys, ct, J, kNoSlot);
     }
-    if (chunk == kStop) return;
+    child_node += uni(J.nodecnt[sz]);
   }
 }
 
@@ -641,7 +653,8 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
             // join only searches that are long already: a task that ends in
             // its first chunks gains nothing from more workers
             const TaskState* ts = P.states + a;
-            if ((ld_relaxed(&ts->np) >> 32) >= P.help_after && ld_relaxed(&ts->best) == kInf) {
+            const uint64_t w = ld_relaxed(&ts->np);
+            if (chunk_index(w) >= P.help_after && !(w & kFound)) {
               fence_acquire();
               next = kActHelp;
               sh.arg = (uint64_t)a;
