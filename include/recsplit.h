@@ -172,13 +172,15 @@ void rs_server_destroy(rs_server *s);
 /*
  * Search schedule: how the seed search hands out attempts, never what it
  * finds (every schedule gives the same structure).  A split search is handed
- * out in chunks of 2^max(0, min(8, tau - chunk_shift)) rounds of 256
- * attempts, tau being the node's Rice parameter (about log2 of its expected
- * attempts), so long searches take few claims and short ones stay shareable.
- * A launch is small when it has fewer than small_tasks_per_worker nodes per
- * worker; small launches use the *_small settings, others the *_large ones.
+ * out in chunks of rounds of 256 attempts; each worker's successive claims
+ * on one search double from one round up to 2^max(0, min(8, tau -
+ * chunk_shift)) rounds, tau being the node's Rice parameter (about log2 of
+ * its expected attempts), so long searches take few claims and short ones
+ * are not overshot.  A launch is small when it has fewer than
+ * small_tasks_per_worker nodes per worker; small launches use the *_small
+ * settings, others the *_large ones.
  *   chunk_shift_*:  see above (0..63)
- *   help_after_*:   chunks a split search must have handed out before idle
+ *   help_after_*:   rounds a split search must have handed out before idle
  *                   workers join it, >= 1
  *   inline_leaf_tau_*: a leaf child whose Rice parameter is below this is
  *                   searched by the worker that split its parent, right after

@@ -30,8 +30,8 @@ from . import keygen, recsplit
 SMALL_SETS = [(10_000, 12, 1000), (30_000, 12, 1000), (20_000, 16, 2000)]
 LARGE_SETS = [(1_000_000, 12, 1000), (10_000_000, 12, 1000), (1_000_000, 8, 100),
               (1_000_000, 16, 2000), (3_000_000, 16, 2000)]
-SHIFTS = (8, 10, 12, 13, 14, 15, 16, 18, 63)
-HELP_AFTER = (1, 2, 4)
+SHIFTS = (10, 12, 13, 14, 15, 16, 63)
+HELP_AFTER = (1, 4, 16, 64)
 INLINE_TAU = (0, 10, 13, 16, 20)
 
 

@@ -115,7 +115,7 @@ struct Task {
 };
 
 struct TaskState {
-  uint64_t np;      // next chunk index (high 32 bits) and chunks in flight (low 32)
+  uint64_t np;      // found bit, rounds handed out, chunks in flight (see rs_search.hip)
   uint64_t best;    // smallest valid value found so far (kInf: none)
   uint32_t closed;  // set by the one worker that finalizes the task
   uint32_t advert;  // 1 while counted in Control::long_tasks, 2 once withdrawn
@@ -174,8 +174,8 @@ struct SearchParams {
   const uint64_t* start;  // starting seed per depth
   uint32_t workers;
   uint32_t stage_cap;  // keys staged in LDS per worker
-  uint32_t chunk_shift;   // a split chunk: 2^clamp(tau - chunk_shift, 0, 8) rounds of 256
-  uint32_t help_after;    // chunks a split search hands out before helpers join
+  uint32_t chunk_shift;   // split claims grow to 2^clamp(tau - chunk_shift, 0, 8) rounds of 256
+  uint32_t help_after;    // rounds a split search hands out before helpers join
   uint32_t inline_leaf_tau;  // leaf children with tau below this skip the queue
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)

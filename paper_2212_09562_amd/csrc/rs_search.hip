@@ -25,7 +25,6 @@ namespace rs {
 
 namespace {
 
-constexpr uint64_t kStop = ~0ull;
 constexpr uint64_t kNoSlot = ~0ull;
 constexpr uint64_t kExhausted = ~0ull - 1;
 
@@ -138,7 +137,8 @@ __device__ Node make_node(const Task& t, const JobDev& J, const uint64_t* start,
   // node that runs past 2^(tau + cap_shift) attempts is a bug, not bad luck
   uint32_t sh = uni((uint32_t)J.tau[c.m]) + cap_shift;
   if (sh < 16) sh = 16;
-  if (sh > 40) sh = 40;
+  // leaves count attempts in 64 bits; a split's claim word counts rounds in 31
+  if (sh > (c.kind == kLeaf ? 40u : 38u)) sh = c.kind == kLeaf ? 40u : 38u;
   c.cap = 1ull << sh;
   return c;
 }
@@ -248,13 +248,14 @@ __device__ __forceinline__ uint64_t round_split_binary(const uint64_t* keys, con
   return ok ? a0 + (uint64_t)__builtin_ctzll(ok) : kInf;
 }
 
-// One chunk: rounds of 256 attempts; a wave stops at its first valid
-// attempt or once its next attempt cannot beat the workgroup's best.
+// One chunk: `rounds` rounds of 256 attempts from round `first` on; a wave
+// stops at its first valid attempt or once its next attempt cannot beat the
+// workgroup's best.
 template <typename RoundFn>
-__device__ __forceinline__ void run_chunk(const uint64_t* keys, const Node& c, uint64_t chunk,
+__device__ __forceinline__ void run_chunk(const uint64_t* keys, const Node& c, uint64_t first,
                                           uint32_t rounds, uint64_t* s_best, RoundFn fn) {
   const uint32_t wave = threadIdx.x >> 6;
-  const uint64_t base = chunk * (uint64_t)(rounds * kWG);
+  const uint64_t base = first * kWG;
   for (uint32_t r = 0; r < rounds; ++r) {
     const uint64_t a0 = base + (uint64_t)r * kWG + wave * 64u;
     const uint64_t cur =
@@ -269,19 +270,19 @@ __device__ __forceinline__ void run_chunk(const uint64_t* keys, const Node& c, u
   }
 }
 
-__device__ void eval_chunk(const uint64_t* keys, const Node& c, uint64_t chunk, uint32_t rounds,
+__device__ void eval_chunk(const uint64_t* keys, const Node& c, uint64_t first, uint32_t rounds,
                            uint64_t* s_best) {
   switch (c.kind) {
     case kLeaf:
-      if (c.rotation) run_chunk(keys, c, chunk, rounds, s_best, round_leaf_rot);
-      else run_chunk(keys, c, chunk, rounds, s_best, round_leaf_brute);
+      if (c.rotation) run_chunk(keys, c, first, rounds, s_best, round_leaf_rot);
+      else run_chunk(keys, c, first, rounds, s_best, round_leaf_brute);
       break;
     case kLower:
     case kUpper:
-      if (c.full) run_chunk(keys, c, chunk, rounds, s_best, round_split_kway<true>);
-      else run_chunk(keys, c, chunk, rounds, s_best, round_split_kway<false>);
+      if (c.full) run_chunk(keys, c, first, rounds, s_best, round_split_kway<true>);
+      else run_chunk(keys, c, first, rounds, s_best, round_split_kway<false>);
       break;
-    default: run_chunk(keys, c, chunk, rounds, s_best, round_split_binary); break;
+    default: run_chunk(keys, c, first, rounds, s_best, round_split_binary); break;
   }
 }
 
@@ -405,13 +406,14 @@ __device__ void finalize_leaf(const SearchParams& P, const Task& t, const JobDev
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // The claim word of a task (TaskState::np): chunks in flight in the low 32
-// bits, the next chunk index in bits 32..62, and bit 63 set once some chunk
-// has produced a value.  Chunks are claimed in increasing order, so a chunk
-// claimed after that bit is set lies wholly above the value and is dropped
-// unevaluated; one atomic both drops an evaluated chunk and claims the next.
+// bits, the rounds of 256 attempts handed out so far (the cursor) in bits
+// 32..62, and bit 63 set once some chunk has produced a value.  A claim of r
+// rounds adds r to the cursor, so chunks are disjoint and handed out in
+// increasing order: a chunk claimed after the bit is set lies wholly above
+// the value and is dropped unevaluated.  One atomic both drops an evaluated
+// chunk and claims the next.
 constexpr uint64_t kFound = 1ull << 63;
-constexpr uint64_t kClaim = 1ull << 32;
-__device__ __forceinline__ uint64_t chunk_index(uint64_t np) { return (np >> 32) & 0x7FFFFFFFull; }
+__device__ __forceinline__ uint64_t cursor(uint64_t np) { return (np >> 32) & 0x7FFFFFFFull; }
 
 // Drop one in-flight chunk of task st; returns true for the one caller that
 // must finalize (a value is known and nothing is in flight any more).
@@ -430,7 +432,8 @@ __device__ __forceinline__ bool release_chunk(TaskState* st) {
 
 struct Shared {
   Task task;
-  uint64_t chunk;
+  uint64_t first;  // first round of the chunk to evaluate
+  uint32_t rounds, go;
   uint64_t best;
   uint64_t fin_value;
   uint32_t action;
@@ -486,29 +489,33 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   Node c = make_node(t, J, P.start, P.cap_shift);
   stage_keys(t, J, c, s_keys, &sh.na);
   __syncthreads();
-  // long searches in long chunks (few claims), short ones in short chunks
-  // (shared early); the Rice parameter is about log2 of the expected attempts
+  // A worker's successive claims on a search double in length, from one round
+  // up to 2^clamp(tau - chunk_shift, 0, 8) rounds (tau, the Rice parameter, is
+  // about log2 of the expected attempts): a search that ends soon is not
+  // overshot, a long one takes few claims.
   const uint32_t tau = uni((uint32_t)J.tau[c.m]);
   const uint32_t e = tau > P.chunk_shift ? (tau - P.chunk_shift < 8 ? tau - P.chunk_shift : 8) : 0;
-  const uint32_t rounds = c.kind == kBinary ? 1u : (1u << e);
-  const uint64_t per_chunk = (uint64_t)rounds * kWG;
+  const uint32_t rmax = c.kind == kBinary ? 1u : (1u << e);
   TaskState* st = P.states + slot;
-  // Thread 0 turns the word returned by a claim into the chunk to evaluate,
-  // or drops the claim (value known, limit passed) and returns kStop.
-  auto decide = [&](uint64_t old) -> uint64_t {
-    const uint64_t ci = chunk_index(old);
+  uint32_t r = 1;  // thread 0: rounds of this worker's next claim
+  // Thread 0 turns the word returned by a claim of rr rounds into the chunk to
+  // evaluate (true), or drops the claim (value known, limit passed).
+  auto decide = [&](uint64_t old, uint32_t rr) -> bool {
+    const uint64_t first = cursor(old);
     if (old & kFound) {
       sh.fin = release_chunk(st) ? 1u : 0u;
-      return kStop;
+      return false;
     }
     // every worker may hold one claimed chunk whose result is not in yet
-    if (ci * per_chunk >= c.cap + (uint64_t)P.workers * per_chunk) {
-      if (set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT))) record_failure(P.ctl, t, slot, st, ci);
+    if (first * kWG >= c.cap + (uint64_t)P.workers * rmax * kWG) {
+      if (set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
+        record_failure(P.ctl, t, slot, st, first);
       sh.fin = release_chunk(st) ? 1u : 0u;
-      return kStop;
+      return false;
     }
-    if (ci == P.help_after) {
-      // a long search: count it so idle workers look for it
+    if (first <= P.help_after && P.help_after < first + rr) {
+      // the claim that takes the search past help_after rounds: count it as
+      // a long search so idle workers look for it
       uint32_t expected = 0;
       if (__hip_atomic_compare_exchange_strong(&st->advert, &expected, 1u, __ATOMIC_RELAXED,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -516,7 +523,9 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
                                __HIP_MEMORY_SCOPE_AGENT);
       wait_memory();  // counted before this chunk can be dropped
     }
-    return ci;
+    sh.first = first;
+    sh.rounds = rr;
+    return true;
   };
   // a helper leaves as soon as the queue slot it holds is ready
   auto leave = [&]() {
@@ -526,21 +535,26 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   if (tid == 0) {
     sh.fin = 0;
     sh.best = kInf;
-    sh.chunk = leave() ? kStop
-                       : decide(__hip_atomic_fetch_add(&st->np, kClaim | 1ull, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT));
+    sh.go = 0;
+    if (!leave()) {
+      sh.go = decide(__hip_atomic_fetch_add(&st->np, ((uint64_t)r << 32) | 1ull, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT),
+                     r)
+                  ? 1u
+                  : 0u;
+      r = r * 2 < rmax ? r * 2 : rmax;
+    }
   }
   for (;;) {
     __syncthreads();  // thread 0's decision is visible
-    const uint64_t chunk = sh.chunk;
-    if (chunk == kStop) break;
-    eval_chunk(s_keys, c, chunk, rounds, &sh.best);
+    if (!sh.go) break;
+    eval_chunk(s_keys, c, sh.first, sh.rounds, &sh.best);
     __syncthreads();  // the chunk's best is final; every thread has read the decision
     if (tid == 0) {
       const uint64_t v = sh.best;
       sh.best = kInf;
       sh.fin = 0;
-      uint64_t next = kStop;
+      sh.go = 0;
       if (v != kInf) {
         __hip_atomic_fetch_min(&st->best, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wait_memory();  // the value is in before the found bit
@@ -551,10 +565,13 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
         sh.fin = release_chunk(st) ? 1u : 0u;
       } else {
         // drop the evaluated chunk and claim the next with one atomic
-        next = decide(__hip_atomic_fetch_add(&st->np, kClaim, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
+        sh.go = decide(__hip_atomic_fetch_add(&st->np, (uint64_t)r << 32, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT),
+                       r)
+                    ? 1u
+                    : 0u;
+        r = r * 2 < rmax ? r * 2 : rmax;
       }
-      sh.chunk = next;
     }
   }
   if (!sh.fin) return;
@@ -654,7 +671,7 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
             // its first chunks gains nothing from more workers
             const TaskState* ts = P.states + a;
             const uint64_t w = ld_relaxed(&ts->np);
-            if (chunk_index(w) >= P.help_after && !(w & kFound)) {
+            if (cursor(w) >= P.help_after && !(w & kFound)) {
               fence_acquire();
               next = kActHelp;
               sh.arg = (uint64_t)a;
