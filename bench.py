@@ -13,7 +13,8 @@ chosen seeds) x 19 VALU instructions per evaluation / search-kernel time
 (HIP events on the kernel's stream); peak = 256 CU x 64 lanes x 2.4 GHz.
 Beside it: the library's live calibration of the same instruction sequence
 with the keys in registers and no memory traffic.  `cpu_baseline` is the
-CPU oracle timed on a bounded sample of the same key set.
+CPU oracle timed on a bounded sample of the same key set, bucket-sharded over
+the host's cores (one single-threaded process per core).
 """
 from __future__ import annotations
 
@@ -76,18 +77,51 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(keys, l, b, buckets):
-    import oracle
+_CPU_SHARD = """
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+keys = np.load(sys.argv[2])
+first, count, l, b = (int(x) for x in sys.argv[3:7])
+t0 = time.perf_counter()
+recs, st = oracle.build_buckets(keys, l, b, True, list(range(first, first + count)))
+dt = time.perf_counter() - t0
+print(json.dumps({"keys": sum(r[1] for r in recs), "seconds": dt,
+                  "evals": st["evals_split"] + st["evals_leaf"]}))
+"""
 
-    t0 = time.perf_counter()
-    recs, st = oracle.build_buckets(keys, l, b, True, buckets)
-    dt = time.perf_counter() - t0
-    nkeys = sum(r[1] for r in recs)
-    return {"value": nkeys / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"buckets {buckets[0]}..{buckets[-1]} ({nkeys} keys) of the same "
-                      f"{len(keys)}-key set, whole construction of those buckets incl. bucketing "
-                      f"all keys, single thread",
-            "seconds": dt, "useful_evals_per_s": (st["evals_split"] + st["evals_leaf"]) / dt}
+
+def cpu_baseline(keys, l, b, per_core, cores):
+    """The CPU oracle on the first per_core * cores buckets of the same key
+    set, bucket-sharded over `cores` single-threaded processes (each
+    buckets all keys, then builds its buckets)."""
+    import subprocess
+    import tempfile
+
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "keys.npy")
+        np.save(path, np.ascontiguousarray(keys))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        t0 = time.perf_counter()
+        procs = [subprocess.Popen([sys.executable, "-c", _CPU_SHARD, ROOT, path, str(i * per_core),
+                                   str(per_core), str(l), str(b)],
+                                  stdout=subprocess.PIPE, text=True, env=env)
+                 for i in range(cores)]
+        outs = [json.loads(p.communicate()[0].strip().splitlines()[-1]) for p in procs]
+        wall = time.perf_counter() - t0
+        if any(p.returncode for p in procs):
+            raise RuntimeError("oracle shard failed")
+    nkeys = sum(o["keys"] for o in outs)
+    slowest = max(o["seconds"] for o in outs)
+    return {"value": nkeys / slowest, "unit": "keys/s", "cores": cores, "kind": "oracle",
+            "sample": f"buckets 0..{per_core * cores - 1} ({nkeys} keys) of the same "
+                      f"{len(keys)}-key set, {cores} single-threaded oracle processes of "
+                      f"{per_core} buckets each (each also buckets all keys); value = keys / "
+                      f"slowest process time",
+            "seconds": slowest, "wall_seconds_incl_startup": wall,
+            "per_core_keys_per_s": nkeys / sum(o["seconds"] for o in outs),
+            "useful_evals_per_s": sum(o["evals"] for o in outs) / slowest}
 
 
 def run_query(f, dev, torch, reps=5):
@@ -128,6 +162,27 @@ def run_sweep(recsplit, keygen, torch, n=1_000_000, leaf_sizes=range(5, 17),
                              "hash_evals_per_s": ev / (st["ms_search"] * 1e-3)})
                 print(f"[sweep] {rows[-1]}", file=sys.stderr, flush=True)
     return {"n": n, "rows": rows}
+
+
+def run_single(recsplit, keygen, torch, l, b, n, seed=31):
+    """One build of n keys (drawn on the device, seed `seed` + l) at leaf size
+    l and bucket size b with rotation fitting, plus a check that the ranks of
+    all keys form a permutation of [0, n)."""
+    keys = keygen.fingerprints_torch(n, seed + l, "cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = recsplit.build(keys, l, b, True)
+    dt = time.perf_counter() - t0
+    st = f.stats()
+    r = f.query(keys)
+    torch.cuda.synchronize()
+    perm = bool(torch.equal(torch.sort(r)[0], torch.arange(n, device=r.device, dtype=r.dtype)))
+    f.free()
+    ev = st["useful_evals_split"] + st["useful_evals_leaf"]
+    return {"n": n, "leaf_size": l, "bucket_size": b, "seconds": dt, "ns_per_key": dt * 1e9 / n,
+            "bits_per_key": st["bytes"] * 8 / n, "ms_search": st["ms_search"],
+            "evals_per_key": ev / n, "hash_evals_per_s": ev / (st["ms_search"] * 1e-3),
+            "ranks_are_permutation": perm}
 
 
 def _search_roofline(evals, ms_search):
@@ -293,7 +348,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=WORKLOAD["n"])
-    ap.add_argument("--cpu-buckets", type=int, default=3)
+    ap.add_argument("--cpu-buckets", type=int, default=3, help="oracle buckets per core")
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="oracle processes (0: the host's cores, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-check", action="store_true",
                     help="run a plain 256 MiB device copy first (byte-counter calibration)")
@@ -306,6 +363,9 @@ def main():
     ap.add_argument("--reserve-per-cu", type=int, default=1)
     ap.add_argument("--sweep", action="store_true",
                     help="instead: leaf size x bucket size x leaf method sweep on 10^6 keys")
+    ap.add_argument("--single", nargs=3, type=int, metavar=("L", "B", "N"), action="append",
+                    help="instead: one rotation-fitting build of N keys at leaf size L, bucket "
+                         "size B (repeatable)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the construction is not "
@@ -318,6 +378,10 @@ def main():
 
     if args.sweep:
         print(json.dumps({"sweep": run_sweep(recsplit, keygen, torch)}), flush=True)
+        return
+    if args.single:
+        for l, b, n in args.single:
+            print(json.dumps({"single": run_single(recsplit, keygen, torch, l, b, n)}), flush=True)
         return
 
     l, b, rot = WORKLOAD["leaf_size"], WORKLOAD["bucket_size"], WORKLOAD["rotation"]
@@ -402,7 +466,8 @@ def main():
                                    args.reserve_per_cu)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(keys, l, b, list(range(args.cpu_buckets)))
+        cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
+        out["cpu_baseline"] = cpu_baseline(keys, l, b, args.cpu_buckets, cores)
     print(json.dumps(out), flush=True)
 
 
