@@ -285,12 +285,14 @@ def _poisson_served(srv, reqs, keys, l, b):
     return lat, wait, span, all(d[0] == 0 for d in done)
 
 
-def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, reserve):
+def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, reserve,
+               load_rates=(60.0, 120.0)):
     """Construction requests with Poisson arrivals (20 per second) and sizes
     log-uniform in [10^4, 10^7] keys, l = 12, b = 1000, rotation fitting
     (seed 5), keys resident in HBM.  Capacity (every request queued at once)
     and latency (requests fed at their arrival times) of the server, against
-    the same requests built by plain rs_build calls one at a time."""
+    the same requests built by plain rs_build calls one at a time; then the
+    same requests arriving faster (load_rates per second)."""
     reqs = keygen.served_requests(count, seed=5)
     keys = [keygen.fingerprints_torch(r["n"], r["seed"], "cuda") for r in reqs]
     torch.cuda.synchronize()
@@ -320,6 +322,20 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, re
         sat_stats = srv.stats()
         lat, wait, span, ok2 = _poisson_served(srv, reqs, keys, l, b)
         st_all = srv.stats()
+        # the same requests arriving faster (arrival times scaled down)
+        sweep = []
+        for rate in load_rates:
+            fast = [dict(r, arrival=r["arrival"] * 20.0 / rate) for r in reqs]
+            s_lat, _, s_span, s_ok = _poisson_served(srv, fast, keys, l, b)
+            ok2 = ok2 and s_ok
+            p_lat, p_span = _poisson_plain(recsplit, fast, keys, l, b)
+            sweep.append({"rate_per_s": rate,
+                          "served": {"latency_ms_p50": _pct(s_lat, 50) * 1e3,
+                                     "latency_ms_p99": _pct(s_lat, 99) * 1e3,
+                                     "keys_per_s": total / s_span},
+                          "plain": {"latency_ms_p50": _pct(p_lat, 50) * 1e3,
+                                    "latency_ms_p99": _pct(p_lat, 99) * 1e3,
+                                    "keys_per_s": total / p_span}})
     sizes = [r["n"] for r in reqs]
     return {"workload": f"{count} requests, Poisson 20/s, sizes log-uniform in [1e4, 1e7] "
                         f"(min {min(sizes)}, max {max(sizes)}), l=12, b=1000, rotation, seed 5",
@@ -339,7 +355,8 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, re
                               "latency_ms_p50": _pct(plain_lat, 50) * 1e3,
                               "latency_ms_p99": _pct(plain_lat, 99) * 1e3},
             "capacity_run": {"launches": sat_stats["launches"],
-                             "peak_bytes": sat_stats["peak_bytes"]}}
+                             "peak_bytes": sat_stats["peak_bytes"]},
+            "load_sweep": sweep}
 
 
 def main():

@@ -107,8 +107,10 @@ int rs_build_batch(const rs_job *jobs, uint32_t njobs, rs_mphf **outs, int *stat
  * max_slots host threads, each with its own non-blocking HIP stream.
  * Requests queue in arrival order; a free slot takes the oldest waiting
  * requests whose combined working memory fits one free region of the pool
- * (up to max_jobs_per_launch of them), builds them together exactly as
- * rs_build_batch does (one persistent search launch), and frees the region.
+ * (up to max_jobs_per_launch of them, and together fewer than 2^20 keys unless
+ * the oldest alone has more: a large request is built alone), builds them
+ * together exactly as rs_build_batch does (one persistent search launch),
+ * and frees the region.
  * Slots run concurrently, so newly arrived requests are admitted while
  * earlier ones are still on the device and their kernels overlap.  A request
  * whose own working memory exceeds the budget is refused at submission

@@ -132,13 +132,19 @@ void slot_loop(rs_server* S, uint32_t slot) {
       for (;;) {
         if (S->stopping) return;
         if (!S->waiting.empty()) {
-          // the oldest requests that fit one free region, in arrival order
+          // the oldest requests that fit one free region, in arrival order;
+          // a large request is built alone and small ones are batched only
+          // while their keys stay below the large-launch size, so no request
+          // waits for the end of a larger one's search
           const size_t room = S->regions.largest();
           std::vector<JobPlan> trial;
           size_t need = 0;
+          uint64_t batch_keys = 0;
           for (uint64_t t : S->waiting) {
             if (trial.size() >= S->cfg.max_jobs_per_launch) break;
             const Request& r = S->reqs[t];
+            if (!trial.empty() && batch_keys + r.job.n >= kLargeLaunchKeys) break;
+            batch_keys += r.job.n;
             JobPlan p;
             p.keys = reinterpret_cast<const Key*>(r.job.keys);
             p.n = r.job.n;
