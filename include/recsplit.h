@@ -107,10 +107,11 @@ int rs_build_batch(const rs_job *jobs, uint32_t njobs, rs_mphf **outs, int *stat
  * max_slots host threads, each with its own non-blocking HIP stream.
  * Requests queue in arrival order; a free slot takes the oldest waiting
  * requests whose combined working memory fits one free region of the pool
- * (up to max_jobs_per_launch of them, and together fewer than 2^20 keys unless
- * the oldest alone has more: a large request is built alone), builds them
- * together exactly as rs_build_batch does (one persistent search launch),
- * and frees the region.
+ * (up to max_jobs_per_launch of them; unless at least max_slots requests are
+ * waiting, together fewer than 2^20 keys or the oldest alone: a large
+ * request is then built alone), builds them together exactly as
+ * rs_build_batch does (one persistent search launch), and frees the
+ * region.
  * Slots run concurrently, so newly arrived requests are admitted while
  * earlier ones are still on the device and their kernels overlap.  A request
  * whose own working memory exceeds the budget is refused at submission
@@ -134,9 +135,10 @@ typedef struct {
   uint32_t max_jobs_per_launch; /* requests per search launch, >= 1 */
   uint32_t reserve_per_cu;      /* search workgroups per compute unit that launches
                                    leave free (0: none); large launches (2^20 keys or
-                                   more) then run one at a time and a small launch
-                                   made while one runs uses only the reserve, so small
-                                   requests do not wait behind large ones */
+                                   more) then run one at a time unless max_slots
+                                   requests are waiting, and a small launch made while
+                                   one runs uses only the reserve, so small requests
+                                   do not wait behind large ones */
 } rs_server_config;
 
 typedef struct {

@@ -102,7 +102,7 @@ struct rs_server {
   uint32_t workers_max = 0;
   uint32_t workers_cap = 0;      // search grid of a launch: the device minus the reserve
   uint32_t reserve_workers = 0;  // the reserve (reserve_per_cu workers on every CU)
-  bool large_running = false;
+  uint32_t large_running = 0;  // large launches in progress
   std::condition_variable cv_large;
   rs_server_stats st{};
   size_t in_use = 0;
@@ -127,15 +127,19 @@ void slot_loop(rs_server* S, uint32_t slot) {
     std::vector<uint64_t> tickets;
     std::vector<JobPlan> plan;
     size_t off = 0, bytes = 0;
+    bool backlog = false;
     {
       std::unique_lock<std::mutex> lock(S->mu);
       for (;;) {
         if (S->stopping) return;
         if (!S->waiting.empty()) {
-          // the oldest requests that fit one free region, in arrival order;
-          // a large request is built alone and small ones are batched only
-          // while their keys stay below the large-launch size, so no request
-          // waits for the end of a larger one's search
+          // The oldest requests that fit one free region, in arrival order.
+          // With a short queue (latency first) a large request is built
+          // alone and small ones are batched only while their keys stay below
+          // the large-launch size, so no request waits for the end of a
+          // larger one's search; with a backlog (at least one request per
+          // slot waiting: throughput first) any requests are batched.
+          backlog = S->waiting.size() >= S->ctx.size();
           const size_t room = S->regions.largest();
           std::vector<JobPlan> trial;
           size_t need = 0;
@@ -143,7 +147,7 @@ void slot_loop(rs_server* S, uint32_t slot) {
           for (uint64_t t : S->waiting) {
             if (trial.size() >= S->cfg.max_jobs_per_launch) break;
             const Request& r = S->reqs[t];
-            if (!trial.empty() && batch_keys + r.job.n >= kLargeLaunchKeys) break;
+            if (!backlog && !trial.empty() && batch_keys + r.job.n >= kLargeLaunchKeys) break;
             batch_keys += r.job.n;
             JobPlan p;
             p.keys = reinterpret_cast<const Key*>(r.job.keys);
@@ -181,11 +185,12 @@ void slot_loop(rs_server* S, uint32_t slot) {
         S->cv_work.wait(lock);
       }
     }
-    // Device sharing.  A large launch holds the device for a long time, so
-    // large launches run one at a time, each leaving the reserve free; a
-    // small launch that starts while a large one runs is sized to the
-    // reserve, so it finishes without waiting for the large one; otherwise a
-    // small launch takes the whole device (it ends soon).
+    // Device sharing.  A large launch holds the device for a long time and
+    // leaves the reserve free; without a backlog large launches run one at a
+    // time (with one, they overlap and fill each other's tails).  A small
+    // launch that starts while a large one runs is sized to the reserve, so
+    // it finishes without waiting for the large one; otherwise a small launch
+    // takes the whole device (it ends soon).
     uint64_t keys = 0;
     for (const JobPlan& p : plan) keys += p.n;
     const bool large = keys >= kLargeLaunchKeys;
@@ -193,8 +198,8 @@ void slot_loop(rs_server* S, uint32_t slot) {
     {
       std::unique_lock<std::mutex> lock(S->mu);
       if (large) {
-        S->cv_large.wait(lock, [&] { return !S->large_running || S->stopping; });
-        S->large_running = true;
+        if (!backlog) S->cv_large.wait(lock, [&] { return !S->large_running || S->stopping; });
+        S->large_running += 1;
         cap = S->workers_cap;
       } else if (S->large_running && S->reserve_workers) {
         cap = S->reserve_workers;
@@ -207,7 +212,7 @@ void slot_loop(rs_server* S, uint32_t slot) {
     }
     if (large) {
       std::lock_guard<std::mutex> lock(S->mu);
-      S->large_running = false;
+      S->large_running -= 1;
     }
     if (large) S->cv_large.notify_all();
     {
