@@ -189,6 +189,10 @@ void rs_server_destroy(rs_server *s);
  *   inline_leaf_tau_*: a leaf child whose Rice parameter is below this is
  *                   searched by the worker that split its parent, right after
  *                   the split, instead of going through the queue (0: never)
+ *   bucket_mode_max_leaf: a launch whose leaf sizes are all at most this,
+ *                   whose buckets hold at most 1152 keys and number at least
+ *                   four per worker is run with one worker per bucket, the
+ *                   whole bucket tree built in LDS (0: never)
  *   max_workers:    cap on the persistent grid (0: the occupancy limit)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
  * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
@@ -197,6 +201,7 @@ typedef struct {
   uint32_t chunk_shift_small, help_after_small, inline_leaf_tau_small;
   uint32_t chunk_shift_large, help_after_large, inline_leaf_tau_large;
   uint32_t small_tasks_per_worker;
+  uint32_t bucket_mode_max_leaf;
   uint32_t max_workers;
 } rs_schedule;
 

@@ -29,10 +29,11 @@ from . import keygen, recsplit
 # (n, leaf size, bucket size) of the key sets each launch class is timed on
 SMALL_SETS = [(10_000, 12, 1000), (30_000, 12, 1000), (20_000, 16, 2000)]
 LARGE_SETS = [(1_000_000, 12, 1000), (10_000_000, 12, 1000), (1_000_000, 8, 100),
-              (1_000_000, 16, 2000), (3_000_000, 16, 2000)]
+              (1_000_000, 10, 500), (1_000_000, 16, 2000), (3_000_000, 16, 2000)]
 SHIFTS = (10, 12, 13, 14, 15, 16, 63)
 HELP_AFTER = (1, 4, 16, 64)
 INLINE_TAU = (0, 10, 13, 16, 20)
+BUCKET_LEAF = (0, 8, 10, 12)
 
 
 def _time_sets(sets, keys, reps, ref=None):
@@ -52,10 +53,11 @@ def _time_sets(sets, keys, reps, ref=None):
 
 
 def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, shifts=SHIFTS, help_after=HELP_AFTER,
-         inline_tau=INLINE_TAU, reps=3, seed=11, tol=0.01, log=None):
+         inline_tau=INLINE_TAU, bucket_leaf=BUCKET_LEAF, reps=3, seed=11, tol=0.01, log=None):
     """Per launch class: the fastest (chunk_shift, help_after), then the
-    fastest inline_leaf_tau with those; returns the schedule dict and the
-    timing table."""
+    fastest inline_leaf_tau with those; then, on the large sets, the
+    whole-bucket threshold (the smallest within tol of the fastest).  Returns
+    the schedule dict and the timing table."""
     import torch
 
     base = recsplit.set_schedule(None)
@@ -102,6 +104,17 @@ def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, shifts=SHIFTS, help_after
             table[cls + "_inline"] = [{"cost": t, "inline_leaf_tau": it} for t, it in results]
             table[cls + "_reference_ms"] = ref
             best[f"inline_leaf_tau_{cls}"] = results[0][1]
+            if cls == "large":
+                results = []
+                for bl in bucket_leaf:
+                    recsplit.set_schedule(best, **force, bucket_mode_max_leaf=bl)
+                    t = _time_sets(sets, ks, reps, ref)
+                    results.append((t, bl))
+                    if log:
+                        log(f"{cls} bucket_mode_max_leaf={bl}: {t:.4f}")
+                table["bucket_mode"] = [{"cost": t, "bucket_mode_max_leaf": bl} for t, bl in results]
+                low = min(t for t, _ in results)
+                best["bucket_mode_max_leaf"] = min(bl for t, bl in results if t <= low * (1.0 + tol))
     finally:
         recsplit.set_schedule(None)
     return best, table

@@ -93,7 +93,7 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
-constexpr rs_schedule kDefaultSchedule = {63, 4, 0, 12, 4, 16, 8, 0};  // autotune.py on an MI355X
+constexpr rs_schedule kDefaultSchedule = {63, 4, 0, 12, 4, 16, 8, 10, 0};
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
@@ -607,12 +607,19 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   }
   if (total >= (1ull << 31) || total > node_cap) return RS_ERR_UNSUPPORTED;
   HIPCHECK(hipEventRecord(c.ev[2], s));
+  // whole-bucket workers for small leaves and small buckets when there are
+  // enough buckets to keep every worker busy
+  bool bucket_mode = sched.bucket_mode_max_leaf != 0 && maxm <= kBucketModeMaxKeys &&
+                     nbk >= 4ull * workers;
+  for (const JobPlan& j : jobs)
+    if (!j.status && j.l > sched.bucket_mode_max_leaf) bucket_mode = false;
 
   // 2. seed search over all nodes of all jobs, one persistent launch
   if (total) {
-    const uint32_t lds = (maxm < 64 ? 64 : maxm) * sizeof(uint64_t);
+    const uint32_t lds =
+        bucket_mode ? bucket_lds_bytes(maxm) : (maxm < 64 ? 64 : maxm) * (uint32_t)sizeof(uint64_t);
     int per_cu = 0;
-    HIPCHECK(search_occupancy(lds, &per_cu));
+    HIPCHECK(search_occupancy(lds, &per_cu, bucket_mode));
     if (per_cu < 1) per_cu = 1;
     const uint32_t occ = (uint32_t)per_cu * (uint32_t)d.cus;
     if (workers > occ) workers = occ;
@@ -662,6 +669,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     P.chunk_shift = small ? sched.chunk_shift_small : sched.chunk_shift_large;
     P.help_after = small ? sched.help_after_small : sched.help_after_large;
     P.inline_leaf_tau = small ? sched.inline_leaf_tau_small : sched.inline_leaf_tau_large;
+    P.bucket_mode = bucket_mode ? 1u : 0u;
     P.cap_shift = 10;
     P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
     HIPCHECK(hipEventRecord(c.ev[3], s));

@@ -164,6 +164,14 @@ struct Control {
 };
 static_assert(sizeof(Control) % 256 == 0, "Control lines");
 
+// Whole-bucket mode: dynamic LDS of a worker = a stack of pending nodes, then
+// per key its hashed word, a scratch word, its A/B class and a scratch class.
+constexpr uint32_t kBucketStackBytes = 64 * 24;
+constexpr uint32_t kBucketModeMaxKeys = 1152;  // largest bucket (LDS of 7 workers per CU)
+__host__ __device__ inline uint32_t bucket_lds_bytes(uint32_t cap) {
+  return kBucketStackBytes + cap * 18u;
+}
+
 struct SearchParams {
   const JobDev* jobs;
   Task* tasks;
@@ -177,6 +185,7 @@ struct SearchParams {
   uint32_t chunk_shift;   // split claims grow to 2^clamp(tau - chunk_shift, 0, 8) rounds of 256
   uint32_t help_after;    // rounds a split search hands out before helpers join
   uint32_t inline_leaf_tau;  // leaf children with tau below this skip the queue
+  uint32_t bucket_mode;      // each root task builds its whole bucket in LDS
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
 };

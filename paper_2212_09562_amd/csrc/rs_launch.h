@@ -31,7 +31,7 @@ hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, ui
                        uint32_t rotation, JobInfo* info, hipStream_t s);
 
 // Seed search (persistent kernel).
-hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, bool bucket_mode = false);
 hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
 
 // Encoding.

@@ -469,9 +469,166 @@ __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, co
   __syncthreads();
 }
 
+// Whole-bucket mode (small leaves, small buckets): a worker builds a whole
+// bucket tree on its own, with the keys resident in LDS.  No node goes
+// through the queue and no key goes back to global memory: a split's keys
+// are partitioned among its children in LDS, and every search is one
+// unbounded chunk, as for a leaf.  Dynamic LDS layout: the stack of pending
+// nodes, then hashed words, their scratch copy, A/B classes, their scratch.
+struct Frame {
+  uint32_t off, m, depth, pad;
+  uint64_t node;
+};
+constexpr uint32_t kFrames = kBucketStackBytes / sizeof(Frame);
+static_assert(kFrames * sizeof(Frame) == kBucketStackBytes, "stack layout");
+
+__device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, const Task& t,
+                           const JobDev& J) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t cap = P.stage_cap;
+  Frame* stack = reinterpret_cast<Frame*>(lds);
+  uint64_t* s_keys = lds + kBucketStackBytes / sizeof(uint64_t);
+  uint64_t* s_tmp = s_keys + cap;
+  uint8_t* s_cls = reinterpret_cast<uint8_t*>(s_tmp + cap);
+  uint8_t* s_ctmp = s_cls + cap;
+  const Key* src = J.keys[0] + t.key_off;
+  for (uint32_t i = tid; i < t.m; i += kWG) {
+    const Key k = src[i];
+    s_keys[i] = k.w1;
+    s_cls[i] = (uint8_t)(k.w0 & 1u);
+  }
+  uint32_t sp = 0, done = 0;  // thread 0: stack depth, nodes finished
+  if (tid == 0) {
+    Frame f;
+    f.off = 0;
+    f.m = t.m;
+    f.depth = t.depth;
+    f.pad = 0;
+    f.node = t.node;
+    stack[0] = f;
+    sp = 1;
+  }
+  for (;;) {
+    __syncthreads();  // the previous node is done; every thread has read its state
+    if (tid == 0) {
+      sh.go = 0;
+      if (sp && ld_relaxed(&P.ctl->error) == 0) {
+        const Frame f = stack[--sp];
+        sh.task.key_off = f.off;
+        sh.task.m = f.m;
+        sh.task.depth = (uint16_t)f.depth;
+        sh.task.node = f.node;
+        sh.go = 1;
+      }
+      sh.best = kInf;
+    }
+    __syncthreads();
+    if (!sh.go) break;
+    Task nt;
+    nt.key_off = uni64(sh.task.key_off);
+    nt.m = uni(sh.task.m);
+    nt.depth = (uint16_t)uni(sh.task.depth);
+    nt.node = uni64(sh.task.node);
+    nt.job = t.job;
+    uint64_t* keys = s_keys + nt.key_off;
+    uint8_t* cls = s_cls + nt.key_off;
+    Node c = make_node(nt, J, P.start, P.cap_shift);
+    if (c.kind == kLeaf && tid < 64) {
+      // the keys of A (class bit clear) first, in a stable order
+      const bool v = lane < c.m;
+      const uint64_t w = v ? keys[lane] : 0;
+      const bool isb = v && cls[lane];
+      const uint64_t bm = __ballot(isb);
+      const uint64_t am = __ballot(v && !isb);
+      const uint32_t na = (uint32_t)__popcll(am);
+      const uint64_t below = mask_below(lane);
+      if (v) keys[isb ? na + (uint32_t)__popcll(bm & below) : (uint32_t)__popcll(am & below)] = w;
+      if (lane == 0) sh.na = na;
+    }
+    __syncthreads();
+    if (c.kind == kLeaf) c.na = uni(sh.na);
+    const uint64_t max_rounds = c.cap / kWG + 1;
+    eval_chunk(keys, c, 0, max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu,
+               &sh.best);
+    __syncthreads();
+    const uint64_t v = sh.best;
+    if (v == kInf) {
+      if (tid == 0 && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
+        record_failure(P.ctl, nt, kNoSlot, P.states, 0);
+      continue;  // the error ends the loop at the next pop
+    }
+    if (c.kind != kLeaf && tid < 64) {
+      // stable partition of the node's keys (with their classes) by child,
+      // through the scratch copy, then back
+      const uint64_t X = c.start + v;
+      uint32_t run = 0;  // lane j: keys already placed in child j
+      for (uint32_t g = 0; g < c.m; g += 64) {
+        const uint32_t i = g + lane;
+        const bool ok = i < c.m;
+        const uint64_t w = ok ? keys[i] : 0;
+        const uint8_t b = ok ? cls[i] : 0;
+        const uint32_t p = reduce(hash_top(w, X), c.m);
+        uint32_t ch = c.kind == kBinary ? (p >= c.unit ? 1u : 0u) : p / c.unit;
+        if (!ok) ch = 0xFFFFFFFFu;
+        const uint32_t at0 = (uint32_t)__shfl((int)run, ok ? (int)ch : 0);
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < c.k; ++j) {
+          const uint64_t mk = __ballot(ch == j);
+          if (ch == j) rank = (uint32_t)__popcll(mk & mask_below(lane));
+          if (lane == j) run += (uint32_t)__popcll(mk);
+        }
+        const uint32_t at = ch * c.unit + at0 + rank;
+        if (ok && at < c.m) {
+          s_tmp[nt.key_off + at] = w;
+          s_ctmp[nt.key_off + at] = b;
+        }
+      }
+      const bool good = lane >= c.k || run == (lane + 1 < c.k ? c.unit : c.last);
+      if (__ballot(!good) != 0 && lane == 0) set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
+      for (uint32_t i = lane; i < c.m; i += 64) {
+        keys[i] = s_tmp[nt.key_off + i];
+        cls[i] = s_ctmp[nt.key_off + i];
+      }
+    }
+    if (tid == 0) {
+      J.vals[nt.node] = v;
+      J.msz[nt.node] = c.m;
+      ++done;
+      if (c.kind != kLeaf) {
+        // children that store a node (any order: a node's index fixes where
+        // its value goes)
+        uint64_t cn = nt.node + 1;
+        for (uint32_t j = 0; j < c.k; ++j) {
+          const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
+          if (sz >= 2) {
+            if (sp >= kFrames || nt.depth + 1 >= kMaxDepth) {
+              set_error(P.ctl, (uint32_t)(-RS_ERR_UNSUPPORTED));
+              break;
+            }
+            Frame f;
+            f.off = (uint32_t)nt.key_off + j * c.unit;
+            f.m = sz;
+            f.depth = nt.depth + 1u;
+            f.pad = 0;
+            f.node = cn;
+            stack[sp++] = f;
+          }
+          cn += J.nodecnt[sz];
+        }
+      }
+    }
+  }
+  if (tid == 0 && done)
+    __hip_atomic_fetch_add(&P.ctl->finished, (uint64_t)done, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+}
+
 // Work on task `slot` until this worker's claim is refused.  my_q (thread 0
 // only) is the queue slot this worker has reserved; a helper leaves as soon
 // as that slot is ready.
+template <bool kBucket>
 __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, uint64_t slot,
                          bool own, uint64_t& my_q) {
   const uint32_t tid = threadIdx.x;
@@ -482,6 +639,10 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   t.depth = (uint16_t)uni(t.depth);
   t.job = (uint16_t)uni(t.job);
   const JobDev& J = P.jobs[t.job];
+  if constexpr (kBucket) {
+    run_bucket(P, sh, s_keys, t, J);
+    return;
+  }
   if (t.m <= uni(J.l)) {
     run_leaf(P, sh, s_keys, t, J, slot);
     return;
@@ -607,7 +768,10 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
 
 }  // namespace
 
-extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams P) {
+// The persistent worker loop; kBucket selects whole-bucket workers (a
+// separate kernel, so the common one keeps its register budget).
+template <bool kBucket>
+__device__ __forceinline__ void search_main(const SearchParams& P) {
   extern __shared__ uint64_t s_keys[];
   __shared__ Shared sh;
   const uint32_t tid = threadIdx.x;
@@ -709,7 +873,7 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
       idle = 0;
     }
     __syncthreads();
-    run_task(P, sh, s_keys, slot, act == kActOwn, my_q);
+    run_task<kBucket>(P, sh, s_keys, slot, act == kActOwn, my_q);
     if (tid == 0 && act == kActOwn) st_relaxed(&P.active[g], (int32_t)-1);
     __syncthreads();
   }
@@ -717,15 +881,28 @@ extern "C" __global__ void __launch_bounds__(kWG) rs_search_kernel(SearchParams 
 
 }  // namespace rs
 
+extern "C" __global__ void __launch_bounds__(rs::kWG) rs_search_kernel(rs::SearchParams P) {
+  rs::search_main<false>(P);
+}
+
+extern "C" __global__ void __launch_bounds__(rs::kWG) rs_bucket_kernel(rs::SearchParams P) {
+  rs::search_main<true>(P);
+}
+
 namespace rs {
 
-hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, rs_search_kernel, kWG,
-                                                      lds_bytes);
+hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, bool bucket_mode) {
+  return bucket_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, rs_bucket_kernel,
+                                                                    kWG, lds_bytes)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, rs_search_kernel,
+                                                                    kWG, lds_bytes);
 }
 
 hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(rs_search_kernel, dim3(grid), dim3(kWG), lds_bytes, s, p);
+  if (p.bucket_mode)
+    hipLaunchKernelGGL(rs_bucket_kernel, dim3(grid), dim3(kWG), lds_bytes, s, p);
+  else
+    hipLaunchKernelGGL(rs_search_kernel, dim3(grid), dim3(kWG), lds_bytes, s, p);
   return hipGetLastError();
 }
 

@@ -93,7 +93,8 @@ class Schedule(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in ("chunk_shift_small", "help_after_small",
                                                 "inline_leaf_tau_small", "chunk_shift_large",
                                                 "help_after_large", "inline_leaf_tau_large",
-                                                "small_tasks_per_worker", "max_workers")]
+                                                "small_tasks_per_worker", "bucket_mode_max_leaf",
+                                                "max_workers")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -119,6 +119,22 @@ def test_device_keygen_matches_host():
         assert np.array_equal(d, keygen.fingerprints(n, seed)), (n, seed)
 
 
+BUCKET_MODE = [(5000, 8, 100, True), (5000, 8, 100, False), (3000, 2, 7, True), (4000, 4, 30, False),
+               (20000, 12, 1000, True), (6000, 10, 60, True), (2000, 16, 20, True), (1500, 5, 1, True)]
+
+
+@pytest.mark.parametrize("n,l,b,rot", BUCKET_MODE)
+def test_whole_bucket_mode(n, l, b, rot):
+    """One worker per bucket, the tree built in LDS (forced with a small grid)."""
+    keys = keygen.fingerprints(n, 300 + n + l)
+    try:
+        rs().set_schedule(None)
+        rs().set_schedule(max_workers=4, bucket_mode_max_leaf=24)
+        _check_parity(keys, l, b, rot, "whole-bucket workers")
+    finally:
+        rs().set_schedule(None)
+
+
 def test_serialise_roundtrip_and_corruption():
     keys = keygen.fingerprints(10000, 13)
     _case("deserialise, n=10000 l=8 b=100")
