@@ -93,7 +93,7 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
-constexpr rs_schedule kDefaultSchedule = {63, 4, 0, 12, 4, 16, 8, 10, 0};
+constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0};  // autotune.py on an MI355X
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
