@@ -55,10 +55,15 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2212_09562_amd", "csrc", f)
 
 
 def kernel_source_hash() -> str:
+    """sha256 of the search kernel's sources with // comments and blank lines
+    removed, so that only code changes invalidate the stored counters."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -5,15 +5,19 @@
 //
 // Scheduling.  Nodes are tasks of a device queue.  The roots of all buckets
 // are queued before the launch; a split that finishes redistributes its keys
-// into its children's ranges and queues them.  Each workgroup (4 wave64) is
-// a worker: it owns one task at a time, stages the task's keys in LDS and
-// tries seeds in chunks of rounds * 256 consecutive attempts, one attempt per
-// lane.  Chunks are claimed with one atomic on the task, so idle workers
-// join a running task (the tail of a geometric search is shared by the whole
-// GPU) and the smallest valid value is still exact: a chunk is evaluated
-// unless it starts above the best value already found, and the task closes
-// when no claimed chunk is left in flight.  Whoever drops the in-flight count
-// to zero with a value known finalizes the task.
+// into its children's ranges and queues them (small leaf children are
+// searched at once by the same worker instead).  Each workgroup (4 wave64)
+// is a worker: it owns one task at a time, stages the task's keys in LDS and
+// tries seeds in rounds of 256 consecutive attempts, one attempt per lane.
+// A leaf is searched by one worker in one go.  A split search is handed out
+// in chunks of rounds through one claim word per task, so idle workers join
+// a long search (the tail of a geometric search is shared by the whole GPU)
+// and the smallest valid value is still exact: chunks are disjoint and
+// handed out in increasing order, a chunk claimed after some value is known
+// lies above it and is dropped, every other chunk is evaluated, and the task
+// closes when no claimed chunk is left in flight.  In whole-bucket mode (a
+// separate kernel instance) each root task builds its bucket's whole tree in
+// LDS instead, with no queue traffic.
 //
 // Minimality (Sec. 5.1: the stored number must be as small as possible):
 // within a round a wave takes the lowest lane whose attempt is valid (ballot
@@ -31,16 +35,8 @@ constexpr uint64_t kExhausted = ~0ull - 1;
 enum : uint32_t { kActExit = 0, kActOwn = 1, kActHelp = 2, kActScan = 3, kActRetry = 4 };
 
 template <typename T>
-__device__ __forceinline__ T ld_acquire(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
 __device__ __forceinline__ T ld_relaxed(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ void st_release(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
 __device__ __forceinline__ void st_relaxed(T* p, T v) {
