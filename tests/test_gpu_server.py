@@ -124,3 +124,34 @@ def test_server_poll_without_waiting():
         f, status, times = res
         assert status == 0 and times["batch_jobs"] == 1 and times["slot"] == 0
         assert f.serialize() == rs().build(keys, 12, 1000, True).serialize()
+
+
+def test_server_large_and_small_requests():
+    """Requests above the large-launch size (2^20 keys) mixed with small ones,
+    first with a short queue (large requests alone and one at a time, small
+    ones beside them on the reserved workgroups), then all queued at once
+    (free batching, overlapping large launches): every result equals its
+    build alone."""
+    import torch
+
+    sizes = [1_100_000, 3000, 20000, 700, 1_300_000, 45000, 9000, 1_050_000, 150]
+    keys = [torch.from_numpy(keygen.fingerprints(n, 80 + i).view(np.int64)).cuda()
+            for i, n in enumerate(sizes)]
+    torch.cuda.synchronize()
+    want = [rs().build(k, 12, 1000, True).serialize() for k in keys]
+    _case(f"server: large and small requests {sizes}")
+    with rs().Server(1 << 30, max_slots=4, max_jobs_per_launch=8, reserve_per_cu=1) as srv:
+        # short queue: one request at a time, each collected before the next
+        for i, k in enumerate(keys[:3]):
+            f, status, _ = srv.wait(srv.submit(k, 12, 1000, True))
+            assert status == 0 and f.serialize() == want[i], i
+        # interleaved while large ones run
+        tickets = [srv.submit(k, 12, 1000, True) for k in keys]
+        results = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    for i, (f, status, times) in enumerate(results):
+        assert status == 0, (i, status)
+        assert f.serialize() == want[i], i
+    assert st["peak_bytes"] <= 1 << 30
+    print(f"[server] launches {st['launches']}, batches "
+          f"{[t['batch_jobs'] for _, _, t in results]}", flush=True)
