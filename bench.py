@@ -119,7 +119,15 @@ def cpu_baseline(keys, l, b, per_core, cores):
             raise RuntimeError("oracle shard failed")
     nkeys = sum(o["keys"] for o in outs)
     slowest = max(o["seconds"] for o in outs)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": nkeys / slowest, "unit": "keys/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
+            "core_seconds": sum(o["seconds"] for o in outs),
             "sample": f"buckets 0..{per_core * cores - 1} ({nkeys} keys) of the same "
                       f"{len(keys)}-key set, {cores} single-threaded oracle processes of "
                       f"{per_core} buckets each (each also buckets all keys); value = keys / "
@@ -367,7 +375,7 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, re
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=WORKLOAD["n"])
     ap.add_argument("--cpu-buckets", type=int, default=3, help="oracle buckets per core")
@@ -423,13 +431,15 @@ def main():
     for _ in range(args.warmup):
         recsplit.build(dev, l, b, rot).free()
     torch.cuda.synchronize()
-    stats = []
+    stats, step_s = [], []
     f = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         if f is not None:
             f.free()
+        a = time.perf_counter()
         f = recsplit.build(dev, l, b, rot)
+        step_s.append(time.perf_counter() - a)
         stats.append(f.stats())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -451,6 +461,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": secs * 1e3 / args.steps,
+        "ms_per_step_median": sorted(step_s)[len(step_s) // 2] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
