@@ -193,6 +193,9 @@ void rs_server_destroy(rs_server *s);
  *                   whose buckets hold at most 1152 keys and number at least
  *                   four per worker is run with one worker per bucket, the
  *                   whole bucket tree built in LDS (0: never)
+ *   stall_guard_us: a search launch in which no node finishes for this
+ *                   long is stopped with RS_ERR_DEVICE (a bug guard; 0: ten
+ *                   seconds)
  *   max_workers:    cap on the persistent grid (0: the occupancy limit)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
  * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
@@ -202,6 +205,7 @@ typedef struct {
   uint32_t chunk_shift_large, help_after_large, inline_leaf_tau_large;
   uint32_t small_tasks_per_worker;
   uint32_t bucket_mode_max_leaf;
+  uint32_t stall_guard_us;
   uint32_t max_workers;
 } rs_schedule;
 

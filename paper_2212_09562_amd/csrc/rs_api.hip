@@ -93,7 +93,7 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
-constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0};  // autotune.py on an MI355X
+constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0};  // autotune.py on an MI355X
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
@@ -671,7 +671,10 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     P.inline_leaf_tau = small ? sched.inline_leaf_tau_small : sched.inline_leaf_tau_large;
     P.bucket_mode = bucket_mode ? 1u : 0u;
     P.cap_shift = 10;
-    P.stall_ticks = (uint64_t)d.wall_khz * 1000ull * 10ull;
+    // s_memrealtime ticks (wall_khz per millisecond)
+    P.stall_ticks = sched.stall_guard_us ? (uint64_t)d.wall_khz * sched.stall_guard_us / 1000ull
+                                         : (uint64_t)d.wall_khz * 1000ull * 10ull;
+    if (P.stall_ticks < 1) P.stall_ticks = 1;
     HIPCHECK(hipEventRecord(c.ev[3], s));
     HIPCHECK(launch_search(P, workers, lds, s));
   } else {

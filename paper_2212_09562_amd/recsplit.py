@@ -94,7 +94,7 @@ class Schedule(ctypes.Structure):
                                                 "inline_leaf_tau_small", "chunk_shift_large",
                                                 "help_after_large", "inline_leaf_tau_large",
                                                 "small_tasks_per_worker", "bucket_mode_max_leaf",
-                                                "max_workers")]
+                                                "stall_guard_us", "max_workers")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

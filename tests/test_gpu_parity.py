@@ -170,6 +170,23 @@ def test_duplicates_and_bad_arguments():
     _check_parity(keys, 8, 100, True, "after errors")
 
 
+def test_stall_guard_stops_a_launch_and_the_library_recovers():
+    """The bug guard on idle time, forced from the host with a 1 microsecond
+    limit: the launch ends with RS_ERR_DEVICE instead of finishing, every
+    worker exits, and the next build is exact."""
+    keys = keygen.fingerprints(20000, 17)
+    _case("stall guard at 1 us")
+    try:
+        rs().set_schedule(None)
+        rs().set_schedule(stall_guard_us=1)
+        with pytest.raises(rs().RecSplitError) as e:
+            rs().build(keys, 12, 1000, True)
+        assert e.value.code == -4
+    finally:
+        rs().set_schedule(None)
+    _check_parity(keys, 12, 1000, True, "after a stopped launch")
+
+
 def test_largest_buckets():
     _case("b=4096, n=12000, l=8")
     _check_parity(keygen.fingerprints(12000, 15), 8, 4096, True)
