@@ -197,6 +197,9 @@ void rs_server_destroy(rs_server *s);
  *                   long is stopped with RS_ERR_DEVICE (a bug guard; 0: ten
  *                   seconds)
  *   max_workers:    cap on the persistent grid (0: the occupancy limit)
+ *   leaf_filter_tau: a leaf whose Rice parameter is at least this is searched
+ *                   in stages that drop an attempt at the first collision
+ *                   within a class of its keys (0: never)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
  * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
  */
@@ -207,6 +210,7 @@ typedef struct {
   uint32_t bucket_mode_max_leaf;
   uint32_t stall_guard_us;
   uint32_t max_workers;
+  uint32_t leaf_filter_tau;
 } rs_schedule;
 
 int rs_set_schedule(const rs_schedule *s);
@@ -244,6 +248,10 @@ typedef struct {
   uint64_t n, nb, nodes, split_nodes, leaf_nodes;
   uint64_t useful_evals_split; /* (s+1) * m per inner node */
   uint64_t useful_evals_leaf;  /* (v+1) * m per brute leaf, (floor(v/m)+1) * m per rotation leaf */
+  /* leaves again, each failed attempt counted at the expected evaluations of
+   * an attempt dropped at the first collision within a class of its keys
+   * (the larger class first; brute force: one class), the successful one at m */
+  double early_exit_evals_leaf;
   uint64_t gr_bits, bytes;
   uint32_t max_bucket, workers;
   double ms_sort, ms_search, ms_encode, ms_total;

@@ -93,7 +93,9 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
-constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0};  // autotune.py on an MI355X
+// autotune.py on an MI355X; leaf_filter_tau = 20 keeps l <= 16 on the plain
+// kernel (the filter gains under 1 % there) and filters l >= 17 (1.7-1.8x)
+constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 20};
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
@@ -479,6 +481,7 @@ int encode_job(Context& c, const Arrays& A, JobPlan& jp, const JobInfo& info, do
   st.leaf_nodes = info.leaves;
   st.useful_evals_split = info.evals_split;
   st.useful_evals_leaf = info.evals_leaf;
+  st.early_exit_evals_leaf = ldexp((double)info.early_exit_leaf_fx, -(int)kLeafWorkShift);
   st.gr_bits = gr_bits;
   st.bytes = nw * 8;
   st.max_bucket = jp.maxm;
@@ -614,12 +617,23 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   for (const JobPlan& j : jobs)
     if (!j.status && j.l > sched.bucket_mode_max_leaf) bucket_mode = false;
 
+  // the filter kernel when some job's full leaves reach leaf_filter_tau
+  bool filter = false;
+  for (const JobPlan& j : jobs)
+    if (!j.status && sched.leaf_filter_tau &&
+        rice_parameter(log_success(make_shape(j.l), j.l)) >= sched.leaf_filter_tau)
+      filter = !bucket_mode;
+  const uint32_t mode = bucket_mode ? kSearchBucket : filter ? kSearchFilter : kSearchNode;
+
   // 2. seed search over all nodes of all jobs, one persistent launch
   if (total) {
-    const uint32_t lds =
-        bucket_mode ? bucket_lds_bytes(maxm) : (maxm < 64 ? 64 : maxm) * (uint32_t)sizeof(uint64_t);
+    // node mode: the largest node's keys, or the queues of a filtered leaf
+    const uint32_t words = filter && maxm < kLeafFilterWords ? kLeafFilterWords
+                           : maxm < 64                       ? 64
+                                                             : maxm;
+    const uint32_t lds = bucket_mode ? bucket_lds_bytes(maxm) : words * (uint32_t)sizeof(uint64_t);
     int per_cu = 0;
-    HIPCHECK(search_occupancy(lds, &per_cu, bucket_mode));
+    HIPCHECK(search_occupancy(lds, &per_cu, mode));
     if (per_cu < 1) per_cu = 1;
     const uint32_t occ = (uint32_t)per_cu * (uint32_t)d.cus;
     if (workers > occ) workers = occ;
@@ -663,14 +677,15 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     P.ctl = A.ctl;
     P.start = d.start;
     P.workers = workers;
-    P.stage_cap = maxm;
+    P.stage_cap = bucket_mode ? maxm : words;
     // chunking of split searches (the result does not depend on it)
     const bool small = total < (uint64_t)sched.small_tasks_per_worker * workers;
     P.chunk_shift = small ? sched.chunk_shift_small : sched.chunk_shift_large;
     P.help_after = small ? sched.help_after_small : sched.help_after_large;
     P.inline_leaf_tau = small ? sched.inline_leaf_tau_small : sched.inline_leaf_tau_large;
-    P.bucket_mode = bucket_mode ? 1u : 0u;
+    P.mode = mode;
     P.cap_shift = 10;
+    P.leaf_filter_tau = filter ? sched.leaf_filter_tau : 0u;
     // s_memrealtime ticks (wall_khz per millisecond)
     P.stall_ticks = sched.stall_guard_us ? (uint64_t)d.wall_khz * sched.stall_guard_us / 1000ull
                                          : (uint64_t)d.wall_khz * 1000ull * 10ull;

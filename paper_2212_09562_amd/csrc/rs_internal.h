@@ -18,6 +18,11 @@ constexpr uint32_t kMaxParts = 16;  // fanout never exceeds 9 for l <= 24
 constexpr uint64_t kInf = ~0ull;
 constexpr uint32_t kWG = 256;  // threads per search worker (4 wave64)
 constexpr uint32_t kWaves = kWG / 64;
+// Filtered leaf search: two queues of kLeafQueue attempts per wave in LDS,
+// after the first kLeafQueueAt words (the leaf's keys).
+constexpr uint32_t kLeafQueue = 128;
+constexpr uint32_t kLeafQueueAt = 32;
+constexpr uint32_t kLeafFilterWords = kLeafQueueAt + kWaves * 2 * kLeafQueue;
 
 enum Kind : uint32_t { kNone = 0, kLeaf = 1, kLower = 2, kUpper = 3, kBinary = 4 };
 
@@ -129,6 +134,15 @@ struct JobInfo {
   uint32_t maxm;
   uint32_t error;
   uint64_t evals_split, evals_leaf, splits, leaves;
+  uint64_t early_exit_leaf_fx;  // see LeafWork; in units of 2^-kLeafWorkShift evaluations
+};
+
+// Expected hash evaluations of one failed leaf attempt of size m when the
+// attempt is dropped at the first collision within a class of its keys (the
+// larger class hashed first), in units of 2^-kLeafWorkShift.
+constexpr uint32_t kLeafWorkShift = 12;
+struct LeafWork {
+  uint32_t fx[kMaxLeaf + 1];
 };
 
 struct JobDev {
@@ -172,6 +186,10 @@ __host__ __device__ inline uint32_t bucket_lds_bytes(uint32_t cap) {
   return kBucketStackBytes + cap * 18u;
 }
 
+// Search kernels: nodes as tasks; the same with filtered leaves; whole
+// buckets per worker.
+enum : uint32_t { kSearchNode = 0, kSearchFilter = 1, kSearchBucket = 2 };
+
 struct SearchParams {
   const JobDev* jobs;
   Task* tasks;
@@ -185,8 +203,9 @@ struct SearchParams {
   uint32_t chunk_shift;   // split claims grow to 2^clamp(tau - chunk_shift, 0, 8) rounds of 256
   uint32_t help_after;    // rounds a split search hands out before helpers join
   uint32_t inline_leaf_tau;  // leaf children with tau below this skip the queue
-  uint32_t bucket_mode;      // each root task builds its whole bucket in LDS
+  uint32_t mode;             // kernel: kSearchNode, kSearchFilter or kSearchBucket
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
+  uint32_t leaf_filter_tau;  // leaves with tau at least this use the filtered search (0: none)
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
 };
 

@@ -30,8 +30,11 @@ hipError_t queue_roots(const uint32_t* cnt, const uint64_t* off, const uint64_t*
 hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, uint32_t l,
                        uint32_t rotation, JobInfo* info, hipStream_t s);
 
+// The LeafWork table of a leaf search mode (host).
+LeafWork leaf_work_table(bool rotation);
+
 // Seed search (persistent kernel).
-hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, bool bucket_mode = false);
+hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, uint32_t mode = kSearchNode);
 hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
 
 // Encoding.

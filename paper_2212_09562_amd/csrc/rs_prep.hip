@@ -198,8 +198,8 @@ __global__ void k_init_states(TaskState* st, uint64_t n) {
 // the node counts.  One atomic per wave.
 __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const uint32_t* msz,
                                                      uint64_t n, uint32_t l, uint32_t rotation,
-                                                     JobInfo* info) {
-  uint64_t es = 0, el = 0, ns = 0, nl = 0;
+                                                     LeafWork lw, JobInfo* info) {
+  uint64_t es = 0, el = 0, ns = 0, nl = 0, ee = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t m = msz[i];
@@ -208,7 +208,9 @@ __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const
       es += (v + 1) * m;
       ns += 1;
     } else {
-      el += ((rotation ? v / m : v) + 1) * m;
+      const uint64_t failed = rotation ? v / m : v;
+      el += (failed + 1) * m;
+      ee += failed * lw.fx[m < kMaxLeaf ? m : kMaxLeaf] + ((uint64_t)m << kLeafWorkShift);
       nl += 1;
     }
   }
@@ -217,20 +219,23 @@ __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const
     el += __shfl_xor(el, d);
     ns += __shfl_xor(ns, d);
     nl += __shfl_xor(nl, d);
+    ee += __shfl_xor(ee, d);
   }
-  __shared__ uint64_t part[4][4];
+  __shared__ uint64_t part[4][5];
   const uint32_t w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     part[w][0] = es;
     part[w][1] = el;
     part[w][2] = ns;
     part[w][3] = nl;
+    part[w][4] = ee;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 5) {
     const uint64_t v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
                        part[3][threadIdx.x];
-    uint64_t* dst[4] = {&info->evals_split, &info->evals_leaf, &info->splits, &info->leaves};
+    uint64_t* dst[5] = {&info->evals_split, &info->evals_leaf, &info->splits, &info->leaves,
+                        &info->early_exit_leaf_fx};
     if (v) atomicAdd(dst[threadIdx.x], v);
   }
 }
@@ -341,8 +346,50 @@ hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s) {
 hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, uint32_t l,
                        uint32_t rotation, JobInfo* info, hipStream_t s) {
   if (!n) return hipSuccess;
-  k_work_counts<<<grid_for(n, 256 * 8, 512), 256, 0, s>>>(vals, msz, n, l, rotation, info);
+  k_work_counts<<<grid_for(n, 256 * 8, 512), 256, 0, s>>>(vals, msz, n, l, rotation,
+                                                          leaf_work_table(rotation != 0), info);
   return hipGetLastError();
+}
+
+// Keys hashed by an attempt that stops at the first collision among j keys
+// thrown into m slots: key i (0-based) is hashed when the first i are
+// distinct, probability prod_{t<i} (1 - t/m).
+static double early_exit_keys(uint32_t j, uint32_t m) {
+  double e = 0.0, distinct = 1.0;
+  for (uint32_t i = 0; i < j; ++i) {
+    e += distinct;
+    distinct *= 1.0 - (double)i / (double)m;
+  }
+  return e;
+}
+
+static double all_distinct(uint32_t j, uint32_t m) {
+  double d = 1.0;
+  for (uint32_t i = 0; i < j; ++i) d *= 1.0 - (double)i / (double)m;
+  return d;
+}
+
+// Brute force: one class of m keys.  Rotation fitting (Sec. 4): class A of
+// a ~ Binomial(m, 1/2) keys and class B of m - a; the larger class is hashed
+// first, the other only when the first has no collision.
+LeafWork leaf_work_table(bool rotation) {
+  LeafWork t;
+  for (uint32_t m = 0; m <= kMaxLeaf; ++m) {
+    double w = 0.0;
+    if (m >= 2 && !rotation) {
+      w = early_exit_keys(m, m);
+    } else if (m >= 2) {
+      double binom = 1.0;  // C(m, a)
+      for (uint32_t a = 0; a <= m; ++a) {
+        const uint32_t n1 = a > m - a ? a : m - a, n2 = m - n1;
+        w += binom * (early_exit_keys(n1, m) + all_distinct(n1, m) * early_exit_keys(n2, m));
+        binom = binom * (double)(m - a) / (double)(a + 1);
+      }
+      w = ldexp(w, -(int)m);
+    }
+    t.fx[m] = (uint32_t)llround(ldexp(w, (int)kLeafWorkShift));
+  }
+  return t;
 }
 
 hipError_t node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* nodecnt, uint64_t* out,

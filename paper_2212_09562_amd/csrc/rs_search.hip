@@ -282,6 +282,134 @@ __device__ void eval_chunk(const uint64_t* keys, const Node& c, uint64_t first, 
   }
 }
 
+// The dynamic LDS of a worker (node mode: the staged keys of the current
+// task; for a filtered leaf also its queues).
+extern __shared__ uint64_t g_lds[];
+
+// ---------------------------------------------------------------- filtered leaves
+// An attempt at a leaf fails at the first collision among the keys of one
+// class (Sec. 4 rules a hash function out by the popcount of a class's
+// word), so most attempts need not hash every key.  Each wave runs its share
+// of the attempts through three stages: stage 1 hashes the first half of the
+// larger class (brute force: of all keys) for 64 new attempts; the attempts
+// without a collision wait in a first queue; stage 2 hashes the rest of that
+// class for 64 waiting attempts at a time, and those still without a
+// collision wait in a second queue; stage 3 hashes the other class and makes
+// the final test (rotation fitting, or for brute force none: m distinct
+// positions are all of them) for 64 at a time.  Both queues are first in,
+// first out, so attempts reach stage 3 in increasing order and the first
+// valid one there is the smallest of every attempt the wave has taken; what
+// is still queued when the wave stops taking attempts is flushed in partial
+// batches.  The value found is the one a search hashing every key of every
+// attempt finds.  A queue entry is (index << 24) | the class word so far,
+// with index = 64 * round + lane within the wave's share.
+
+__device__ __forceinline__ uint32_t leaf_bits(const uint64_t* keys, uint32_t lo, uint32_t hi,
+                                              uint64_t X, uint32_t m) {
+  uint32_t mask = 0;
+#pragma unroll 4
+  for (uint32_t i = lo; i < hi; ++i) mask |= 1u << reduce(hash_top(keys[i], X), m);
+  return mask;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Append the entries of the lanes with `keep` to queue q at tail t.
+__device__ __forceinline__ void queue_push(uint64_t* q, uint32_t& t, bool keep, uint64_t e) {
+  const uint64_t km = __ballot(keep);
+  if (keep) q[(t + (uint32_t)__popcll(km & mask_below(lane_id()))) & (kLeafQueue - 1)] = e;
+  t += (uint32_t)__popcll(km);
+}
+
+// One leaf searched from attempt 0 for at most `rounds` rounds (256 attempts
+// each), with its keys at the start of the dynamic LDS and this wave's two
+// queues after them.  A stage whose queue holds fewer than 64 attempts still
+// runs once its oldest attempt has waited `patience` rounds, so that a valid
+// attempt is not held back long past the end of a short search or by a
+// selective stage (a lopsided A/B split makes stage 2 pass few attempts).
+__device__ void run_leaf_filtered(const Node& c, uint32_t rounds, uint32_t patience,
+                                               uint64_t* s_best) {
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint64_t lane_base = (uint64_t)wave * 64u;
+  const uint64_t* keys = g_lds;
+  uint64_t* q1 = g_lds + kLeafQueueAt + wave * 2 * kLeafQueue;
+  uint64_t* q2 = q1 + kLeafQueue;
+  // class 1 = [lo1, hi1), hashed in stages 1 ([lo1, mid)) and 2; class 2 =
+  // [lo2, hi2) in stage 3.  Keys of A are staged first.
+  const bool a_first = !c.rotation || 2 * c.na >= c.m;
+  const uint32_t lo1 = a_first ? 0u : c.na;
+  const uint32_t hi1 = !c.rotation ? c.m : (a_first ? c.na : c.m);
+  const uint32_t lo2 = !c.rotation ? c.m : (a_first ? c.na : 0u);
+  const uint32_t hi2 = !c.rotation ? c.m : (a_first ? c.m : c.na);
+  const uint32_t mid = lo1 + (hi1 - lo1 + 1) / 2;
+  uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;  // queue heads and tails (wave-uniform)
+  auto attempt_of = [&](uint64_t idx) { return (idx >> 6) * kWG + lane_base + (idx & 63u); };
+  auto stage2 = [&](uint32_t cnt) {
+    const bool v = lane < cnt;
+    const uint64_t e = v ? q1[(h1 + lane) & (kLeafQueue - 1)] : 0;
+    h1 += cnt;
+    const uint64_t idx = e >> 24;
+    const uint64_t X = c.start + attempt_of(idx) * c.mult;
+    const uint32_t w = ((uint32_t)e & 0xFFFFFFu) | leaf_bits(keys, mid, hi1, X, c.m);
+    queue_push(q2, t2, v && (uint32_t)__popc(w) == hi1 - lo1, (idx << 24) | w);
+  };
+  auto stage3 = [&](uint32_t cnt) -> uint64_t {
+    const bool v = lane < cnt;
+    const uint64_t e = v ? q2[(h2 + lane) & (kLeafQueue - 1)] : 0;
+    h2 += cnt;
+    const uint64_t att = attempt_of(e >> 24);
+    const uint32_t w1 = (uint32_t)e & 0xFFFFFFu;
+    const uint32_t w2 = leaf_bits(keys, lo2, hi2, c.start + att * c.mult, c.m);
+    uint64_t cm = __ballot(v && (uint32_t)__popc(w2) == hi2 - lo2);
+    if (!c.rotation) return cm ? readlane64(att, (uint32_t)__builtin_ctzll(cm)) : kInf;
+    while (cm) {
+      const uint32_t L = (uint32_t)__builtin_ctzll(cm);
+      const uint32_t x1 = __builtin_amdgcn_readlane(w1, L);
+      const uint32_t x2 = __builtin_amdgcn_readlane(w2, L);
+      const uint32_t want = ~(a_first ? x1 : x2) & c.fullmask;
+      const uint32_t b = a_first ? x2 : x1;
+      const bool ok = lane < c.m && rot_m(b, lane < c.m ? lane : 0, c.m, c.fullmask) == want;
+      const uint64_t okm = __ballot(ok);
+      if (okm) return readlane64(att, L) * c.m + (uint64_t)__builtin_ctzll(okm);
+      cm &= cm - 1;
+    }
+    return kInf;
+  };
+  uint64_t found = kInf;
+  uint32_t wait1 = 0, wait2 = 0;  // rounds the oldest entry of each queue has waited
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint64_t a0 = (uint64_t)r * kWG + lane_base;
+    const uint64_t cur =
+        uni64(__hip_atomic_load(s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (a0 * c.mult >= cur) break;
+    const uint32_t w = leaf_bits(keys, lo1, mid, c.start + (a0 + lane) * c.mult, c.m);
+    queue_push(q1, t1, (uint32_t)__popc(w) == mid - lo1, (((uint64_t)r * 64u + lane) << 24) | w);
+    wait1 = t1 != h1 ? wait1 + 1 : 0;
+    if (t1 - h1 >= 64 || (t1 != h1 && wait1 >= patience)) {
+      stage2(t1 - h1 < 64 ? t1 - h1 : 64);
+      wait1 = 0;
+    }
+    wait2 = t2 != h2 ? wait2 + 1 : 0;
+    if (t2 - h2 >= 64 || (t2 != h2 && wait2 >= patience)) {
+      found = stage3(t2 - h2 < 64 ? t2 - h2 : 64);
+      wait2 = 0;
+      if (found != kInf) break;
+    }
+  }
+  while (found == kInf && t1 != h1) {
+    stage2(t1 - h1 < 64 ? t1 - h1 : 64);
+    if (t2 - h2 >= 64) found = stage3(64);
+  }
+  while (found == kInf && t2 != h2) found = stage3(t2 - h2 < 64 ? t2 - h2 : 64);
+  if (found != kInf && lane == 0)
+    __hip_atomic_fetch_min(s_best, found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Stage the task's keys in LDS.  Leaves put the keys of A (bit 0 of w0 clear)
 // first, in a stable order, and report |A|.
 __device__ void stage_keys(const Task& t, const JobDev& J, const Node& c, uint64_t* s_keys,
@@ -443,6 +571,7 @@ struct Shared {
 // A leaf is short and there are many: one worker searches it alone, as one
 // chunk without a bound on its rounds, with no global traffic until the value
 // is known.  Nobody joins a leaf (its state is never claimed).
+template <bool kFilter>
 __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
                          const JobDev& J, uint64_t slot) {
   const uint32_t tid = threadIdx.x;
@@ -452,8 +581,18 @@ __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, co
   __syncthreads();
   c.na = uni(sh.na);
   const uint64_t max_rounds = c.cap / kWG + 1;
-  eval_chunk(s_keys, c, 0, max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu,
-             &sh.best);
+  const uint32_t rounds = max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu;
+  // long leaf searches go through the filter (the queues sit in the staging
+  // area, after the leaf's keys)
+  const uint32_t tau = uni((uint32_t)J.tau[c.m]);
+  if (kFilter && P.leaf_filter_tau && P.stage_cap >= kLeafFilterWords &&
+      tau >= P.leaf_filter_tau) {
+    // patience: 1/32 of the expected rounds (2^tau values, mult per attempt), 1 to 16
+    const uint64_t expect = (1ull << (tau < 40 ? tau : 40)) / ((uint64_t)c.mult * kWG);
+    const uint64_t pat = expect >> 5;
+    run_leaf_filtered(c, rounds, pat < 1 ? 1u : (pat > 16 ? 16u : (uint32_t)pat), &sh.best);
+  } else
+    eval_chunk(s_keys, c, 0, rounds, &sh.best);
   __syncthreads();
   const uint64_t v = sh.best;
   if (v == kInf) {
@@ -624,7 +763,7 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
 // Work on task `slot` until this worker's claim is refused.  my_q (thread 0
 // only) is the queue slot this worker has reserved; a helper leaves as soon
 // as that slot is ready.
-template <bool kBucket>
+template <uint32_t kMode>
 __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, uint64_t slot,
                          bool own, uint64_t& my_q) {
   const uint32_t tid = threadIdx.x;
@@ -635,12 +774,12 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   t.depth = (uint16_t)uni(t.depth);
   t.job = (uint16_t)uni(t.job);
   const JobDev& J = P.jobs[t.job];
-  if constexpr (kBucket) {
+  if constexpr (kMode == kSearchBucket) {
     run_bucket(P, sh, s_keys, t, J);
     return;
   }
   if (t.m <= uni(J.l)) {
-    run_leaf(P, sh, s_keys, t, J, slot);
+    run_leaf<kMode == kSearchFilter>(P, sh, s_keys, t, J, slot);
     return;
   }
   Node c = make_node(t, J, P.start, P.cap_shift);
@@ -756,7 +895,7 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       ct.m = sz;
       ct.depth = (uint16_t)(t.depth + 1);
       ct.job = t.job;
-      run_leaf(P, sh, s_keys, ct, J, kNoSlot);
+      run_leaf<kMode == kSearchFilter>(P, sh, s_keys, ct, J, kNoSlot);
     }
     child_node += uni(J.nodecnt[sz]);
   }
@@ -764,9 +903,10 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
 
 }  // namespace
 
-// The persistent worker loop; kBucket selects whole-bucket workers (a
-// separate kernel, so the common one keeps its register budget).
-template <bool kBucket>
+// The persistent worker loop, one kernel per mode (kSearchNode, kSearchFilter
+// with filtered leaves, kSearchBucket with whole-bucket workers), so that
+// each keeps its own register budget.
+template <uint32_t kMode>
 __device__ __forceinline__ void search_main(const SearchParams& P) {
   extern __shared__ uint64_t s_keys[];
   __shared__ Shared sh;
@@ -869,7 +1009,7 @@ __device__ __forceinline__ void search_main(const SearchParams& P) {
       idle = 0;
     }
     __syncthreads();
-    run_task<kBucket>(P, sh, s_keys, slot, act == kActOwn, my_q);
+    run_task<kMode>(P, sh, s_keys, slot, act == kActOwn, my_q);
     if (tid == 0 && act == kActOwn) st_relaxed(&P.active[g], (int32_t)-1);
     __syncthreads();
   }
@@ -878,28 +1018,36 @@ __device__ __forceinline__ void search_main(const SearchParams& P) {
 }  // namespace rs
 
 extern "C" __global__ void __launch_bounds__(rs::kWG) rs_search_kernel(rs::SearchParams P) {
-  rs::search_main<false>(P);
+  rs::search_main<rs::kSearchNode>(P);
+}
+
+// seven waves per SIMD, as the plain kernel has: the filter's state goes to
+// scalar spill lanes rather than costing occupancy
+extern "C" __global__ void __launch_bounds__(rs::kWG) __attribute__((amdgpu_waves_per_eu(7)))
+rs_filter_kernel(rs::SearchParams P) {
+  rs::search_main<rs::kSearchFilter>(P);
 }
 
 extern "C" __global__ void __launch_bounds__(rs::kWG) rs_bucket_kernel(rs::SearchParams P) {
-  rs::search_main<true>(P);
+  rs::search_main<rs::kSearchBucket>(P);
 }
 
 namespace rs {
 
-hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, bool bucket_mode) {
-  return bucket_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, rs_bucket_kernel,
-                                                                    kWG, lds_bytes)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, rs_search_kernel,
-                                                                    kWG, lds_bytes);
+static const void* search_kernel(uint32_t mode) {
+  return mode == kSearchBucket   ? reinterpret_cast<const void*>(rs_bucket_kernel)
+         : mode == kSearchFilter ? reinterpret_cast<const void*>(rs_filter_kernel)
+                                 : reinterpret_cast<const void*>(rs_search_kernel);
+}
+
+hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, uint32_t mode) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel(mode), kWG,
+                                                      lds_bytes);
 }
 
 hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s) {
-  if (p.bucket_mode)
-    hipLaunchKernelGGL(rs_bucket_kernel, dim3(grid), dim3(kWG), lds_bytes, s, p);
-  else
-    hipLaunchKernelGGL(rs_search_kernel, dim3(grid), dim3(kWG), lds_bytes, s, p);
-  return hipGetLastError();
+  void* args[] = {const_cast<SearchParams*>(&p)};
+  return hipLaunchKernel(search_kernel(p.mode), dim3(grid), dim3(kWG), args, lds_bytes, s);
 }
 
 }  // namespace rs

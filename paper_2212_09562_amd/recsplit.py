@@ -42,7 +42,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("nb", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
                 ("split_nodes", ctypes.c_uint64), ("leaf_nodes", ctypes.c_uint64),
                 ("useful_evals_split", ctypes.c_uint64), ("useful_evals_leaf", ctypes.c_uint64),
-                ("gr_bits", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("early_exit_evals_leaf", ctypes.c_double), ("gr_bits", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
                 ("max_bucket", ctypes.c_uint32), ("workers", ctypes.c_uint32),
                 ("ms_sort", ctypes.c_double), ("ms_search", ctypes.c_double),
                 ("ms_encode", ctypes.c_double), ("ms_total", ctypes.c_double)]
@@ -94,7 +94,8 @@ class Schedule(ctypes.Structure):
                                                 "inline_leaf_tau_small", "chunk_shift_large",
                                                 "help_after_large", "inline_leaf_tau_large",
                                                 "small_tasks_per_worker", "bucket_mode_max_leaf",
-                                                "stall_guard_us", "max_workers")]
+                                                "stall_guard_us", "max_workers",
+                                                "leaf_filter_tau")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

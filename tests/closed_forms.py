@@ -101,3 +101,29 @@ def fanouts_exact(l: int):
     lo = max(2, math.ceil(Fraction(35 * l + 55, 100)))
     up = max(2, math.ceil(Fraction(21 * l + 90, 100)))
     return lo, up
+
+
+def _distinct_prefix(j: int, m: int) -> float:
+    """P(j keys hashed uniformly into m slots are pairwise distinct)."""
+    return math.prod(1 - t / m for t in range(j))
+
+
+def early_exit_keys(j: int, m: int) -> float:
+    """Keys hashed when j keys are hashed in turn until the first collision."""
+    return sum(_distinct_prefix(i, m) for i in range(j))
+
+
+def leaf_early_exit_evals(m: int, rotation: bool) -> float:
+    """Expected evaluations of one leaf attempt that stops at the first
+    collision within a class: brute force has one class of m keys; rotation
+    fitting has A, |A| ~ Binomial(m, 1/2), and B, the larger hashed first and
+    the other only when the first has no collision (Sec. 4: a class's word
+    rules the attempt out by its popcount)."""
+    if not rotation:
+        return early_exit_keys(m, m)
+    tot = 0.0
+    for a in range(m + 1):
+        n1 = max(a, m - a)
+        tot += math.comb(m, a) / 2 ** m * (early_exit_keys(n1, m) +
+                                           _distinct_prefix(n1, m) * early_exit_keys(m - n1, m))
+    return tot

@@ -135,6 +135,51 @@ def test_whole_bucket_mode(n, l, b, rot):
         rs().set_schedule(None)
 
 
+FILTERED = [(5000, 8, 100, True), (5000, 8, 100, False), (3000, 2, 7, True), (4000, 4, 30, False),
+            (20000, 12, 1000, True), (3000, 12, 200, False), (2500, 16, 2000, True),
+            (400, 18, 50, True), (1500, 5, 1, True)]
+
+
+@pytest.mark.parametrize("n,l,b,rot", FILTERED)
+def test_filtered_leaf_search(n, l, b, rot):
+    """Every leaf of three or more keys through the staged early-exit search
+    (leaf_filter_tau=1), then none (0): the same bytes as the oracle."""
+    keys = keygen.fingerprints(n, 500 + n + l)
+    try:
+        for tau in (1, 0):
+            rs().set_schedule(None)
+            rs().set_schedule(leaf_filter_tau=tau)
+            _check_parity(keys, l, b, rot, f"leaf_filter_tau={tau}")
+    finally:
+        rs().set_schedule(None)
+
+
+def test_early_exit_leaf_work_figure():
+    """The early-exit leaf work the library reports equals the closed form
+    summed over the oracle's leaf values."""
+    from closed_forms import leaf_early_exit_evals
+
+    for n, l, b, rot in ((20000, 12, 500, True), (20000, 8, 100, False), (4000, 16, 2000, True)):
+        keys = keygen.fingerprints(n, 41)
+        _case(f"early-exit work n={n} l={l} b={b} rot={rot}")
+        data, _ = oracle.build(keys, l, b, rot)
+        f = rs().build(keys, l, b, rot)
+        nb = oracle.num_buckets(len(keys), b)
+        sizes = np.bincount([oracle.bucket_of(int(w0), nb) for w0 in keys[:, 0]], minlength=nb)
+        want = 0.0
+        for j in range(nb):
+            vals = oracle.bucket_values(data, j)
+            ms = oracle.preorder_sizes(int(sizes[j]), l)
+            assert len(ms) == len(vals)
+            for m, v in zip(ms, vals):
+                if m <= l:
+                    failed = int(v) // m if rot else int(v)
+                    want += failed * leaf_early_exit_evals(m, rot) + m
+        got = f.stats()["early_exit_evals_leaf"]
+        assert got == pytest.approx(want, rel=2e-4), (l, b, rot)
+        assert got < f.stats()["useful_evals_leaf"]
+
+
 def test_serialise_roundtrip_and_corruption():
     keys = keygen.fingerprints(10000, 13)
     _case("deserialise, n=10000 l=8 b=100")
