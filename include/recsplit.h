@@ -200,6 +200,10 @@ void rs_server_destroy(rs_server *s);
  *   leaf_filter_tau: a leaf whose Rice parameter is at least this is searched
  *                   in stages that drop an attempt at the first collision
  *                   within a class of its keys (0: never)
+ *   join_leaf_tau:  in a small launch, a leaf whose Rice parameter is at
+ *                   least this is searched in claimed chunks, as splits are,
+ *                   so that idle workers join it (only together with the
+ *                   leaf filter; 0: never; other leaves have one worker each)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
  * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
  */
@@ -211,6 +215,7 @@ typedef struct {
   uint32_t stall_guard_us;
   uint32_t max_workers;
   uint32_t leaf_filter_tau;
+  uint32_t join_leaf_tau;
 } rs_schedule;
 
 int rs_set_schedule(const rs_schedule *s);

@@ -94,8 +94,10 @@ std::mutex g_devices_mu;
 Context g_default[64];
 
 // autotune.py on an MI355X; leaf_filter_tau = 20 keeps l <= 16 on the plain
-// kernel (the filter gains under 1 % there) and filters l >= 17 (1.7-1.8x)
-constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 20};
+// kernel (the filter gains under 1 % there) and filters l >= 17 (1.7-1.8x);
+// join_leaf_tau = 22: leaves of 18 keys and more are joined in small launches
+// (3x to 6x on a few thousand leaves of 22 or 24 keys)
+constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 20, 22};
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
@@ -686,6 +688,9 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     P.mode = mode;
     P.cap_shift = 10;
     P.leaf_filter_tau = filter ? sched.leaf_filter_tau : 0u;
+    // joined leaves pay claims and queue flushes per chunk: worth it only when
+    // the leaves are too few to keep every worker busy to the end
+    P.join_leaf_tau = small ? sched.join_leaf_tau : 0u;
     // s_memrealtime ticks (wall_khz per millisecond)
     P.stall_ticks = sched.stall_guard_us ? (uint64_t)d.wall_khz * sched.stall_guard_us / 1000ull
                                          : (uint64_t)d.wall_khz * 1000ull * 10ull;

@@ -206,6 +206,7 @@ struct SearchParams {
   uint32_t mode;             // kernel: kSearchNode, kSearchFilter or kSearchBucket
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
   uint32_t leaf_filter_tau;  // leaves with tau at least this use the filtered search (0: none)
+  uint32_t join_leaf_tau;    // leaves with tau at least this are searched in claimed chunks (0: none)
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
 };
 

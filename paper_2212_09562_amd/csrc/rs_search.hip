@@ -133,8 +133,8 @@ __device__ Node make_node(const Task& t, const JobDev& J, const uint64_t* start,
   // node that runs past 2^(tau + cap_shift) attempts is a bug, not bad luck
   uint32_t sh = uni((uint32_t)J.tau[c.m]) + cap_shift;
   if (sh < 16) sh = 16;
-  // leaves count attempts in 64 bits; a split's claim word counts rounds in 31
-  if (sh > (c.kind == kLeaf ? 40u : 38u)) sh = c.kind == kLeaf ? 40u : 38u;
+  // a claim word counts rounds (256 attempts) in 31 bits
+  if (sh > 38u) sh = 38u;
   c.cap = 1ull << sh;
   return c;
 }
@@ -325,17 +325,18 @@ __device__ __forceinline__ void queue_push(uint64_t* q, uint32_t& t, bool keep, 
   t += (uint32_t)__popcll(km);
 }
 
-// One leaf searched from attempt 0 for at most `rounds` rounds (256 attempts
-// each), with its keys at the start of the dynamic LDS and this wave's two
-// queues after them.  A stage whose queue holds fewer than 64 attempts still
-// runs once its oldest attempt has waited `patience` rounds, so that a valid
-// attempt is not held back long past the end of a short search or by a
-// selective stage (a lopsided A/B split makes stage 2 pass few attempts).
-__device__ void run_leaf_filtered(const Node& c, uint32_t rounds, uint32_t patience,
-                                               uint64_t* s_best) {
+// One chunk of a leaf search, `rounds` rounds of 256 attempts from round
+// `first` on, with the leaf's keys at the start of the dynamic LDS and this
+// wave's two queues after them.  A stage whose queue holds fewer than 64
+// attempts still runs once its oldest attempt has waited `patience` rounds,
+// so that a valid attempt is not held back long past the end of a short
+// search or by a selective stage (a lopsided A/B split makes stage 2 pass few
+// attempts).
+__device__ void run_leaf_filtered(const Node& c, uint64_t first, uint32_t rounds,
+                                  uint32_t patience, uint64_t* s_best) {
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x >> 6;
-  const uint64_t lane_base = (uint64_t)wave * 64u;
+  const uint64_t lane_base = first * kWG + (uint64_t)wave * 64u;
   const uint64_t* keys = g_lds;
   uint64_t* q1 = g_lds + kLeafQueueAt + wave * 2 * kLeafQueue;
   uint64_t* q2 = q1 + kLeafQueue;
@@ -568,9 +569,23 @@ struct Shared {
   int32_t pick;
 };
 
-// A leaf is short and there are many: one worker searches it alone, as one
-// chunk without a bound on its rounds, with no global traffic until the value
-// is known.  Nobody joins a leaf (its state is never claimed).
+__device__ __forceinline__ bool filtered_leaf(const SearchParams& P, uint32_t tau) {
+  return P.leaf_filter_tau && P.stage_cap >= kLeafFilterWords && tau >= P.leaf_filter_tau;
+}
+
+// Rounds a filter queue waits: 1/32 of the leaf's expected rounds (about 2^tau
+// values, mult per attempt), 1 to 16.
+__device__ __forceinline__ uint32_t patience(const Node& c, uint32_t tau) {
+  const uint64_t expect = (1ull << (tau < 40 ? tau : 40)) / ((uint64_t)c.mult * kWG);
+  const uint64_t pat = expect >> 5;
+  return pat < 1 ? 1u : (pat > 16 ? 16u : (uint32_t)pat);
+}
+
+// Most leaves are short and there are many: one worker searches such a leaf
+// alone, as one chunk without a bound on its rounds, with no global traffic
+// until the value is known (its state is never claimed).  Leaves whose Rice
+// parameter reaches join_leaf_tau go through the claimed chunks of run_task
+// instead, so that idle workers can join them.
 template <bool kFilter>
 __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
                          const JobDev& J, uint64_t slot) {
@@ -585,13 +600,9 @@ __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, co
   // long leaf searches go through the filter (the queues sit in the staging
   // area, after the leaf's keys)
   const uint32_t tau = uni((uint32_t)J.tau[c.m]);
-  if (kFilter && P.leaf_filter_tau && P.stage_cap >= kLeafFilterWords &&
-      tau >= P.leaf_filter_tau) {
-    // patience: 1/32 of the expected rounds (2^tau values, mult per attempt), 1 to 16
-    const uint64_t expect = (1ull << (tau < 40 ? tau : 40)) / ((uint64_t)c.mult * kWG);
-    const uint64_t pat = expect >> 5;
-    run_leaf_filtered(c, rounds, pat < 1 ? 1u : (pat > 16 ? 16u : (uint32_t)pat), &sh.best);
-  } else
+  if (kFilter && filtered_leaf(P, tau))
+    run_leaf_filtered(c, 0, rounds, patience(c, tau), &sh.best);
+  else
     eval_chunk(s_keys, c, 0, rounds, &sh.best);
   __syncthreads();
   const uint64_t v = sh.best;
@@ -760,31 +771,21 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
   __syncthreads();
 }
 
-// Work on task `slot` until this worker's claim is refused.  my_q (thread 0
-// only) is the queue slot this worker has reserved; a helper leaves as soon
-// as that slot is ready.
-template <uint32_t kMode>
-__device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, uint64_t slot,
-                         bool own, uint64_t& my_q) {
+// Search task t (queue slot `slot`) in claimed chunks until this worker's
+// claim is refused, and finalize it if this worker drops the last chunk in
+// flight.  my_q (thread 0 only) is the queue slot this worker has reserved; a
+// helper leaves as soon as that slot is ready.  kLeafTask: a long leaf (the
+// filter kernel only), instantiated apart so that the split searches keep
+// their registers.
+template <uint32_t kMode, bool kLeafTask>
+__device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
+                            const JobDev& J, uint64_t slot, bool own, uint64_t& my_q) {
   const uint32_t tid = threadIdx.x;
-  Task t = sh.task;
-  t.key_off = uni64(t.key_off);
-  t.node = uni64(t.node);
-  t.m = uni(t.m);
-  t.depth = (uint16_t)uni(t.depth);
-  t.job = (uint16_t)uni(t.job);
-  const JobDev& J = P.jobs[t.job];
-  if constexpr (kMode == kSearchBucket) {
-    run_bucket(P, sh, s_keys, t, J);
-    return;
-  }
-  if (t.m <= uni(J.l)) {
-    run_leaf<kMode == kSearchFilter>(P, sh, s_keys, t, J, slot);
-    return;
-  }
+  constexpr bool leaf = kLeafTask;
   Node c = make_node(t, J, P.start, P.cap_shift);
   stage_keys(t, J, c, s_keys, &sh.na);
   __syncthreads();
+  if (leaf) c.na = uni(sh.na);
   // A worker's successive claims on a search double in length, from one round
   // up to 2^clamp(tau - chunk_shift, 0, 8) rounds (tau, the Rice parameter, is
   // about log2 of the expected attempts): a search that ends soon is not
@@ -844,7 +845,10 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   for (;;) {
     __syncthreads();  // thread 0's decision is visible
     if (!sh.go) break;
-    eval_chunk(s_keys, c, sh.first, sh.rounds, &sh.best);
+    if (leaf && filtered_leaf(P, tau))
+      run_leaf_filtered(c, sh.first, sh.rounds, patience(c, tau), &sh.best);
+    else
+      eval_chunk(s_keys, c, sh.first, sh.rounds, &sh.best);
     __syncthreads();  // the chunk's best is final; every thread has read the decision
     if (tid == 0) {
       const uint64_t v = sh.best;
@@ -881,6 +885,11 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
   }
   __syncthreads();
   const uint64_t v = sh.fin_value;
+  if constexpr (leaf) {
+    finalize_leaf(P, t, J, c, v);
+    __syncthreads();
+    return;
+  }
   if (tid < 64) finalize_split(P, t, J, c, v);
   __syncthreads();
   // the leaf children kept out of the queue, searched here in order
@@ -898,6 +907,36 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       run_leaf<kMode == kSearchFilter>(P, sh, s_keys, ct, J, kNoSlot);
     }
     child_node += uni(J.nodecnt[sz]);
+  }
+}
+
+// Work on the task in queue slot `slot` (own: this worker took it from the
+// queue; otherwise it joins another worker's search).
+template <uint32_t kMode>
+__device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, uint64_t slot,
+                         bool own, uint64_t& my_q) {
+  Task t = sh.task;
+  t.key_off = uni64(t.key_off);
+  t.node = uni64(t.node);
+  t.m = uni(t.m);
+  t.depth = (uint16_t)uni(t.depth);
+  t.job = (uint16_t)uni(t.job);
+  const JobDev& J = P.jobs[t.job];
+  if constexpr (kMode == kSearchBucket) {
+    run_bucket(P, sh, s_keys, t, J);
+  } else {
+    if (t.m > uni(J.l)) {
+      run_claimed<kMode, false>(P, sh, s_keys, t, J, slot, own, my_q);
+      return;
+    }
+    if constexpr (kMode == kSearchFilter) {
+      // long leaves (what the filter kernel is chosen for) can be joined
+      if (P.join_leaf_tau && uni((uint32_t)J.tau[t.m]) >= P.join_leaf_tau) {
+        run_claimed<kMode, true>(P, sh, s_keys, t, J, slot, own, my_q);
+        return;
+      }
+    }
+    run_leaf<kMode == kSearchFilter>(P, sh, s_keys, t, J, slot);
   }
 }
 

@@ -95,7 +95,7 @@ class Schedule(ctypes.Structure):
                                                 "help_after_large", "inline_leaf_tau_large",
                                                 "small_tasks_per_worker", "bucket_mode_max_leaf",
                                                 "stall_guard_us", "max_workers",
-                                                "leaf_filter_tau")]
+                                                "leaf_filter_tau", "join_leaf_tau")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

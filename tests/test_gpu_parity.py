@@ -143,13 +143,17 @@ FILTERED = [(5000, 8, 100, True), (5000, 8, 100, False), (3000, 2, 7, True), (40
 @pytest.mark.parametrize("n,l,b,rot", FILTERED)
 def test_filtered_leaf_search(n, l, b, rot):
     """Every leaf of three or more keys through the staged early-exit search
-    (leaf_filter_tau=1), then none (0): the same bytes as the oracle."""
+    (leaf_filter_tau=1), alone or in claimed chunks that idle workers join
+    (join_leaf_tau=1; with leaf_filter_tau=12 the shorter leaves are joined
+    unfiltered), then none: the same bytes as the oracle."""
     keys = keygen.fingerprints(n, 500 + n + l)
     try:
-        for tau in (1, 0):
+        for filt, join in ((1, 0), (1, 1), (12, 1), (0, 0)):
             rs().set_schedule(None)
-            rs().set_schedule(leaf_filter_tau=tau)
-            _check_parity(keys, l, b, rot, f"leaf_filter_tau={tau}")
+            # joining happens in small launches: make every launch small
+            rs().set_schedule(leaf_filter_tau=filt, join_leaf_tau=join,
+                              small_tasks_per_worker=1000)
+            _check_parity(keys, l, b, rot, f"leaf_filter_tau={filt} join_leaf_tau={join}")
     finally:
         rs().set_schedule(None)
 
