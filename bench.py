@@ -65,7 +65,7 @@ def attempt_evals(st):
 
 
 WORKLOAD = {"n": 10_000_000, "leaf_size": 16, "bucket_size": 2000, "rotation": True, "seed": 3}
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "rs_search_kernel.l16_b2000_n1e7.pmc.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "rs_filter_kernel.l16_b2000_n1e7.pmc.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2212_09562_amd", "csrc", f)
                   for f in ("rs_search.hip", "rs_internal.h")]
 
@@ -490,7 +490,7 @@ def main():
                    "global_batch": n, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "rs_search_kernel", "ms_per_launch": ms_search,
+                     "kernel": "rs_filter_kernel", "ms_per_launch": ms_search,
                      "useful_hash_evals": evals, "attempt_hash_evals": attempt_evals(st),
                      "ops_per_eval": OPS_PER_EVAL,
                      "hash_evals_per_s": evals_per_s,

@@ -93,11 +93,12 @@ Device g_dev[64];
 std::mutex g_devices_mu;
 Context g_default[64];
 
-// autotune.py on an MI355X; leaf_filter_tau = 20 keeps l <= 16 on the plain
-// kernel (the filter gains under 1 % there) and filters l >= 17 (1.7-1.8x);
+// autotune.py on an MI355X; leaf_filter_tau = 19 filters leaves of 16 keys and
+// more (l = 16, b = 2000: 0.9 %; b = 100: 6 %; l = 18 and 20: 1.7-1.8x) and
+// keeps smaller leaf sizes on the plain kernel (their leaves are too short);
 // join_leaf_tau = 22: leaves of 18 keys and more are joined in small launches
 // (3x to 6x on a few thousand leaves of 22 or 24 keys)
-constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 20, 22};
+constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 19, 22};
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
