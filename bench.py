@@ -51,12 +51,13 @@ assert sum(INSTRUCTION_MIX.values()) == OPS_PER_EVAL
 
 
 def algorithmic_evals(st):
-    """Hash evaluations the search must make: (s+1) m per split; per leaf, m
-    for the valid attempt and, for each failed one, the expected evaluations
-    of an attempt dropped at the first collision within a class of its keys
-    (the paper counts m per rotation attempt, fig:hashFunctionEvals; an
-    attempt ruled out early needs fewer)."""
-    return st["useful_evals_split"] + st["early_exit_evals_leaf"]
+    """Hash evaluations the search must make: per node, m for the valid
+    attempt and, for each failed one, the expected evaluations of an attempt
+    dropped at the first evidence that it fails (a collision within a class
+    of a leaf's keys; a lower or upper split child above its part size;
+    fanout-2 splits all m).  The paper counts m per attempt
+    (fig:hashFunctionEvals); an attempt ruled out early needs fewer."""
+    return st["early_exit_evals_split"] + st["early_exit_evals_leaf"]
 
 
 def attempt_evals(st):

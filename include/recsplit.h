@@ -200,6 +200,9 @@ void rs_server_destroy(rs_server *s);
  *   leaf_filter_tau: a leaf whose Rice parameter is at least this is searched
  *                   in stages that drop an attempt at the first collision
  *                   within a class of its keys (0: never)
+ *   split_filter_tau: a lower or upper split search whose Rice parameter is
+ *                   at least this drops an attempt once a child holds more
+ *                   keys than its part size (0: never)
  *   join_leaf_tau:  in a small launch, a leaf whose Rice parameter is at
  *                   least this is searched in claimed chunks, as splits are,
  *                   so that idle workers join it (only together with the
@@ -216,6 +219,7 @@ typedef struct {
   uint32_t max_workers;
   uint32_t leaf_filter_tau;
   uint32_t join_leaf_tau;
+  uint32_t split_filter_tau;
 } rs_schedule;
 
 int rs_set_schedule(const rs_schedule *s);
@@ -257,6 +261,11 @@ typedef struct {
    * an attempt dropped at the first collision within a class of its keys
    * (the larger class first; brute force: one class), the successful one at m */
   double early_exit_evals_leaf;
+  /* splits again, each failed lower or upper split attempt counted at the
+   * expected evaluations of an attempt dropped once a child holds more keys
+   * than its part size (rs_attempt_work), fanout-2 attempts and the
+   * successful one at m */
+  double early_exit_evals_split;
   uint64_t gr_bits, bytes;
   uint32_t max_bucket, workers;
   double ms_sort, ms_search, ms_encode, ms_total;
@@ -281,6 +290,18 @@ typedef struct {
 } rs_valu_rates;
 
 int rs_calibrate_valu(rs_valu_rates *out);
+
+/*
+ * Measurement helper for the work counts (host only, no device needed):
+ * expected hash evaluations of one failed attempt at a node of node_size
+ * keys in a tree of leaf size leaf_size, when the attempt stops at the first
+ * evidence that it fails -- a leaf (node_size <= leaf_size) at the first
+ * collision within a class of its keys (flags: RS_FLAG_ROTATION for the A/B
+ * classes of rotation fitting, else one class), a lower or upper split once
+ * a child holds more keys than its part size, a fanout-2 split not at all
+ * (node_size).  -1 for arguments out of range.
+ */
+double rs_attempt_work(uint32_t leaf_size, uint32_t node_size, uint32_t flags);
 
 void rs_free(rs_mphf *f);
 

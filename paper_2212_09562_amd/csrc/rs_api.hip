@@ -97,14 +97,25 @@ Context g_default[64];
 // more (l = 16, b = 2000: 0.9 %; b = 100: 6 %; l = 18 and 20: 1.7-1.8x) and
 // keeps smaller leaf sizes on the plain kernel (their leaves are too short);
 // join_leaf_tau = 22: leaves of 18 keys and more are joined in small launches
-// (3x to 6x on a few thousand leaves of 22 or 24 keys)
-constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 19, 22};
+// (3x to 6x on a few thousand leaves of 22 or 24 keys); split_filter_tau = 16:
+// l = 16, b = 2000 8 % faster, while the shorter split searches of l <= 12
+// lose 1.5-2.6 % to it
+constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 19, 22, 16};
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
 rs_schedule current_schedule() {
   std::lock_guard<std::mutex> lock(g_schedule_mu);
   return g_schedule;
+}
+
+// split_work_table per leaf size, computed once per process
+const std::vector<double>& split_work_cached(uint32_t l) {
+  static std::mutex mu;
+  static std::vector<double> tables[kMaxLeaf + 1];
+  std::lock_guard<std::mutex> lock(mu);
+  if (tables[l].empty()) tables[l] = split_work_table(l);
+  return tables[l];
 }
 
 int tables_for(Device& d, uint32_t l, Tables** out) {
@@ -114,15 +125,21 @@ int tables_for(Device& d, uint32_t l, Tables** out) {
     std::vector<uint32_t> nc, fb;
     std::vector<uint8_t> tau;
     compute_tables(l, nc, fb, tau);
-    uint32_t *a = nullptr, *b = nullptr;
+    const std::vector<double>& sw = split_work_cached(l);
+    std::vector<uint32_t> swfx(kTable);
+    for (uint32_t m = 0; m < kTable; ++m) swfx[m] = (uint32_t)llround(ldexp(sw[m], kLeafWorkShift));
+    uint32_t *a = nullptr, *b = nullptr, *w = nullptr;
     uint8_t* c = nullptr;
     HIPCHECK(hipMalloc(&a, kTable * sizeof(uint32_t)));
     HIPCHECK(hipMalloc(&b, kTable * sizeof(uint32_t)));
+    HIPCHECK(hipMalloc(&w, kTable * sizeof(uint32_t)));
     HIPCHECK(hipMalloc(&c, kTable));
     HIPCHECK(hipMemcpy(a, nc.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b, fb.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(w, swfx.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(c, tau.data(), kTable, hipMemcpyHostToDevice));
     t.fixedbits = b;
+    t.split_work = w;
     t.tau = c;
     t.nodecnt = a;  // last: a non-null nodecnt means the table is complete
   }
@@ -485,6 +502,7 @@ int encode_job(Context& c, const Arrays& A, JobPlan& jp, const JobInfo& info, do
   st.useful_evals_split = info.evals_split;
   st.useful_evals_leaf = info.evals_leaf;
   st.early_exit_evals_leaf = ldexp((double)info.early_exit_leaf_fx, -(int)kLeafWorkShift);
+  st.early_exit_evals_split = ldexp((double)info.early_exit_split_fx, -(int)kLeafWorkShift);
   st.gr_bits = gr_bits;
   st.bytes = nw * 8;
   st.max_bucket = jp.maxm;
@@ -620,20 +638,31 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   for (const JobPlan& j : jobs)
     if (!j.status && j.l > sched.bucket_mode_max_leaf) bucket_mode = false;
 
-  // the filter kernel when some job's full leaves reach leaf_filter_tau
+  // the filter kernel when split searches are filtered or some job's full
+  // leaves reach leaf_filter_tau; LDS for the largest node's keys and for the
+  // queues of a filtered leaf or split
   bool filter = false;
-  for (const JobPlan& j : jobs)
-    if (!j.status && sched.leaf_filter_tau &&
-        rice_parameter(log_success(make_shape(j.l), j.l)) >= sched.leaf_filter_tau)
-      filter = !bucket_mode;
+  uint32_t words = maxm < 64 ? 64 : maxm;
+  for (const JobPlan& j : jobs) {
+    if (j.status || bucket_mode) continue;
+    const Shape sh = make_shape(j.l);
+    const bool leaves = sched.leaf_filter_tau &&
+                        rice_parameter(log_success(sh, j.l)) >= sched.leaf_filter_tau;
+    const bool splits = sched.split_filter_tau &&
+                        (rice_parameter(log_success(sh, sh.la)) >= sched.split_filter_tau ||
+                         rice_parameter(log_success(sh, sh.ua)) >= sched.split_filter_tau);
+    if (leaves || splits) filter = true;
+    if (leaves && words < kLeafFilterWords) words = kLeafFilterWords;
+    if (splits) {
+      const uint32_t ua = sh.ua;
+      const uint32_t need = split_queue_at(ua < j.maxm ? ua : j.maxm) + kSplitQueueWords;
+      if (words < need) words = need;
+    }
+  }
   const uint32_t mode = bucket_mode ? kSearchBucket : filter ? kSearchFilter : kSearchNode;
 
   // 2. seed search over all nodes of all jobs, one persistent launch
   if (total) {
-    // node mode: the largest node's keys, or the queues of a filtered leaf
-    const uint32_t words = filter && maxm < kLeafFilterWords ? kLeafFilterWords
-                           : maxm < 64                       ? 64
-                                                             : maxm;
     const uint32_t lds = bucket_mode ? bucket_lds_bytes(maxm) : words * (uint32_t)sizeof(uint64_t);
     int per_cu = 0;
     HIPCHECK(search_occupancy(lds, &per_cu, mode));
@@ -692,6 +721,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     // joined leaves pay claims and queue flushes per chunk: worth it only when
     // the leaves are too few to keep every worker busy to the end
     P.join_leaf_tau = small ? sched.join_leaf_tau : 0u;
+    P.split_filter_tau = filter ? sched.split_filter_tau : 0u;
     // s_memrealtime ticks (wall_khz per millisecond)
     P.stall_ticks = sched.stall_guard_us ? (uint64_t)d.wall_khz * sched.stall_guard_us / 1000ull
                                          : (uint64_t)d.wall_khz * 1000ull * 10ull;
@@ -723,7 +753,8 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
       const JobPlan& j = jobs[i];
       if (j.status || !j.total) continue;
       HIPCHECK(work_counts(A.vals + j.node_off, A.msz + j.node_off, j.total, j.l,
-                           (j.flags & RS_FLAG_ROTATION) ? 1u : 0u, A.jinfo + i, s));
+                           (j.flags & RS_FLAG_ROTATION) ? 1u : 0u, j.T->split_work,
+                           A.jinfo + i, s));
     }
   HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
   float ms_sort = 0, ms_search = 0;
@@ -988,6 +1019,17 @@ int rs_set_schedule(const rs_schedule* sc) {
   std::lock_guard<std::mutex> lock(g_schedule_mu);
   g_schedule = v;
   return RS_OK;
+}
+
+double rs_attempt_work(uint32_t leaf_size, uint32_t node_size, uint32_t flags) {
+  if (leaf_size < 2 || leaf_size > kMaxLeaf || node_size < 2 || node_size >= kTable ||
+      (flags & ~RS_FLAG_ROTATION))
+    return -1.0;
+  if (node_size <= leaf_size) {
+    const LeafWork t = leaf_work_table((flags & RS_FLAG_ROTATION) != 0);
+    return ldexp((double)t.fx[node_size], -(int)kLeafWorkShift);
+  }
+  return split_work_cached(leaf_size)[node_size];
 }
 
 int rs_get_schedule(rs_schedule* sc) {

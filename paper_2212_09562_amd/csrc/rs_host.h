@@ -11,11 +11,13 @@
 namespace rs {
 
 // Per-leaf-size tables, m = 0 .. kMaxBucketKeys: stored nodes of a subtree,
-// Golomb-Rice fixed bits of a subtree, and the Rice parameter of a node.
+// Golomb-Rice fixed bits of a subtree, the Rice parameter of a node, and the
+// expected evaluations of a failed split attempt (for the work counts).
 struct Tables {
   uint32_t* nodecnt = nullptr;
   uint32_t* fixedbits = nullptr;
   uint8_t* tau = nullptr;
+  uint32_t* split_work = nullptr;  // split_work_table in units of 2^-kLeafWorkShift
 };
 
 // Read-only after initialisation; shared by every context on the device.

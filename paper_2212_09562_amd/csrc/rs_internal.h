@@ -23,6 +23,10 @@ constexpr uint32_t kWaves = kWG / 64;
 constexpr uint32_t kLeafQueue = 128;
 constexpr uint32_t kLeafQueueAt = 32;
 constexpr uint32_t kLeafFilterWords = kLeafQueueAt + kWaves * 2 * kLeafQueue;
+// Filtered split search: three such queues per wave after the node's keys
+// (rounded up to 32 words).
+constexpr uint32_t kSplitQueueWords = kWaves * 3 * kLeafQueue;
+__host__ __device__ inline uint32_t split_queue_at(uint32_t m) { return (m + 31u) & ~31u; }
 
 enum Kind : uint32_t { kNone = 0, kLeaf = 1, kLower = 2, kUpper = 3, kBinary = 4 };
 
@@ -134,7 +138,8 @@ struct JobInfo {
   uint32_t maxm;
   uint32_t error;
   uint64_t evals_split, evals_leaf, splits, leaves;
-  uint64_t early_exit_leaf_fx;  // see LeafWork; in units of 2^-kLeafWorkShift evaluations
+  uint64_t early_exit_leaf_fx;   // see LeafWork; in units of 2^-kLeafWorkShift evaluations
+  uint64_t early_exit_split_fx;  // the same for splits (split_work_table)
 };
 
 // Expected hash evaluations of one failed leaf attempt of size m when the
@@ -207,6 +212,8 @@ struct SearchParams {
   uint32_t cap_shift;    // bug guard: a node may try 2^(tau + cap_shift) attempts
   uint32_t leaf_filter_tau;  // leaves with tau at least this use the filtered search (0: none)
   uint32_t join_leaf_tau;    // leaves with tau at least this are searched in claimed chunks (0: none)
+  uint32_t split_filter_tau;  // lower/upper splits with tau at least this drop attempts at an
+                              // overfull child (0: never)
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
 };
 

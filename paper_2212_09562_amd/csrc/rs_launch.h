@@ -1,6 +1,8 @@
 // Host-side launchers of the library's kernels (one translation unit each).
 #pragma once
 
+#include <vector>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -26,12 +28,18 @@ hipError_t queue_roots(const uint32_t* cnt, const uint64_t* off, const uint64_t*
                        uint64_t nb, uint32_t job, uint64_t key_base, uint64_t node_off, Task* tasks,
                        uint32_t* ready, Control* ctl, hipStream_t s);
 
-// Useful hash evaluations and node counts of a finished search (added to *info).
+// Useful hash evaluations and node counts of a finished search (added to
+// *info); split_fx: expected evaluations of a failed split attempt per node
+// size, in units of 2^-kLeafWorkShift.
 hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, uint32_t l,
-                       uint32_t rotation, JobInfo* info, hipStream_t s);
+                       uint32_t rotation, const uint32_t* split_fx, JobInfo* info, hipStream_t s);
 
 // The LeafWork table of a leaf search mode (host).
 LeafWork leaf_work_table(bool rotation);
+
+// Expected evaluations of a failed split attempt, per node size m <
+// kTable, for leaf size l (0 for leaf sizes; host).
+std::vector<double> split_work_table(uint32_t l);
 
 // Seed search (persistent kernel).
 hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, uint32_t mode = kSearchNode);

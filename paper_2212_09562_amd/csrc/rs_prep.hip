@@ -1,6 +1,9 @@
 // Bucketing (Sec. 2.2: keys to buckets of expected size b, sorted by bucket,
 // bucket borders), device-wide exclusive scans, the duplicate check, and the
 // roots of the search queue.
+#include <algorithm>
+#include <vector>
+
 #include "rs_launch.h"
 
 namespace rs {
@@ -198,14 +201,16 @@ __global__ void k_init_states(TaskState* st, uint64_t n) {
 // the node counts.  One atomic per wave.
 __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const uint32_t* msz,
                                                      uint64_t n, uint32_t l, uint32_t rotation,
-                                                     LeafWork lw, JobInfo* info) {
-  uint64_t es = 0, el = 0, ns = 0, nl = 0, ee = 0;
+                                                     LeafWork lw, const uint32_t* split_fx,
+                                                     JobInfo* info) {
+  uint64_t es = 0, el = 0, ns = 0, nl = 0, ee = 0, se = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t m = msz[i];
     const uint64_t v = vals[i];
     if (m > l) {
       es += (v + 1) * m;
+      se += v * split_fx[m < kTable ? m : kTable - 1] + ((uint64_t)m << kLeafWorkShift);
       ns += 1;
     } else {
       const uint64_t failed = rotation ? v / m : v;
@@ -220,8 +225,9 @@ __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const
     ns += __shfl_xor(ns, d);
     nl += __shfl_xor(nl, d);
     ee += __shfl_xor(ee, d);
+    se += __shfl_xor(se, d);
   }
-  __shared__ uint64_t part[4][5];
+  __shared__ uint64_t part[4][6];
   const uint32_t w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     part[w][0] = es;
@@ -229,13 +235,14 @@ __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const
     part[w][2] = ns;
     part[w][3] = nl;
     part[w][4] = ee;
+    part[w][5] = se;
   }
   __syncthreads();
-  if (threadIdx.x < 5) {
+  if (threadIdx.x < 6) {
     const uint64_t v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
                        part[3][threadIdx.x];
-    uint64_t* dst[5] = {&info->evals_split, &info->evals_leaf, &info->splits, &info->leaves,
-                        &info->early_exit_leaf_fx};
+    uint64_t* dst[6] = {&info->evals_split, &info->evals_leaf, &info->splits, &info->leaves,
+                        &info->early_exit_leaf_fx, &info->early_exit_split_fx};
     if (v) atomicAdd(dst[threadIdx.x], v);
   }
 }
@@ -344,10 +351,10 @@ hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s) {
 }
 
 hipError_t work_counts(const uint64_t* vals, const uint32_t* msz, uint64_t n, uint32_t l,
-                       uint32_t rotation, JobInfo* info, hipStream_t s) {
+                       uint32_t rotation, const uint32_t* split_fx, JobInfo* info, hipStream_t s) {
   if (!n) return hipSuccess;
-  k_work_counts<<<grid_for(n, 256 * 8, 512), 256, 0, s>>>(vals, msz, n, l, rotation,
-                                                          leaf_work_table(rotation != 0), info);
+  k_work_counts<<<grid_for(n, 256 * 8, 512), 256, 0, s>>>(
+      vals, msz, n, l, rotation, leaf_work_table(rotation != 0), split_fx, info);
   return hipGetLastError();
 }
 
@@ -367,6 +374,66 @@ static double all_distinct(uint32_t j, uint32_t m) {
   double d = 1.0;
   for (uint32_t i = 0; i < j; ++i) d *= 1.0 - (double)i / (double)m;
   return d;
+}
+
+// Lower and upper splits: after t keys the child counts are multinomial with
+// probabilities (part size)/m; an attempt is alive while every count is at
+// most its part size, and key t+1 is hashed while it is alive.  Independent
+// Poisson counts with the part sizes as means, conditioned on their sum t,
+// have that multinomial law, so P(alive after t) = [x^t] prod_j T_j(x) /
+// Poisson(t; m), T_j the Poisson(u_j) pmf truncated at u_j.  Parts other
+// than the last are all of one size, so their product is shared by the
+// node sizes with the same part count.  Long double: for m near 1300 the
+// pmfs reach e^-1300.  Fanout-2 splits are credited all m keys.
+std::vector<double> split_work_table(uint32_t l) {
+  const Shape s = make_shape(l);
+  std::vector<double> w(kTable, 0.0);
+  auto pmf = [](uint32_t u) {
+    std::vector<long double> p(u + 1);
+    for (uint32_t c = 0; c <= u; ++c)
+      p[c] = expl((long double)c * logl((long double)u) - (long double)u - lgammal(c + 1.0L));
+    return p;
+  };
+  auto mul = [](const std::vector<long double>& a, const std::vector<long double>& b, size_t cap) {
+    std::vector<long double> r(std::min(a.size() + b.size() - 1, cap), 0.0L);
+    for (size_t i = 0; i < a.size() && i < cap; ++i)
+      for (size_t j = 0; j < b.size() && i + j < cap; ++j) r[i + j] += a[i] * b[j];
+    return r;
+  };
+  // shared products of f full parts, per part size
+  std::vector<long double> base;
+  uint32_t base_u = 0, base_f = 0;
+  std::vector<long double> full_pmf;
+  for (uint32_t m = 2; m < kTable; ++m) {
+    const uint32_t kd = kind_of(s, m);
+    if (kd == kLeaf) continue;
+    if (kd == kBinary) {
+      w[m] = (double)m;
+      continue;
+    }
+    const Parts p = parts_of(s, m);
+    const uint32_t u = p.unit, f = p.k - 1;
+    if (u != base_u) {
+      base_u = u;
+      base_f = 0;
+      base.assign(1, 1.0L);
+      full_pmf = pmf(u);
+    }
+    while (base_f < f) {
+      base = mul(base, full_pmf, (size_t)kTable);
+      ++base_f;
+    }
+    const std::vector<long double> conv = mul(base, pmf(p.last), (size_t)m);
+    long double e = 0.0L;
+    for (uint32_t t = 0; t < m; ++t) {
+      const long double pois =
+          expl((long double)t * logl((long double)m) - (long double)m - lgammal(t + 1.0L));
+      const long double alive = t < conv.size() ? conv[t] / pois : 0.0L;
+      e += alive < 1.0L ? alive : 1.0L;
+    }
+    w[m] = (double)e;
+  }
+  return w;
 }
 
 // Brute force: one class of m keys.  Rotation fitting (Sec. 4): class A of

@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("nb", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
                 ("split_nodes", ctypes.c_uint64), ("leaf_nodes", ctypes.c_uint64),
                 ("useful_evals_split", ctypes.c_uint64), ("useful_evals_leaf", ctypes.c_uint64),
-                ("early_exit_evals_leaf", ctypes.c_double), ("gr_bits", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("early_exit_evals_leaf", ctypes.c_double),
+                ("early_exit_evals_split", ctypes.c_double), ("gr_bits", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
                 ("max_bucket", ctypes.c_uint32), ("workers", ctypes.c_uint32),
                 ("ms_sort", ctypes.c_double), ("ms_search", ctypes.c_double),
                 ("ms_encode", ctypes.c_double), ("ms_total", ctypes.c_double)]
@@ -87,6 +88,8 @@ class Job(ctypes.Structure):
 _lib.rs_build_batch.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(_vp),
                                 ctypes.POINTER(ctypes.c_int)]
 _lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
+_lib.rs_attempt_work.argtypes = [_u32, _u32, _u32]
+_lib.rs_attempt_work.restype = ctypes.c_double
 
 
 class Schedule(ctypes.Structure):
@@ -95,7 +98,8 @@ class Schedule(ctypes.Structure):
                                                 "help_after_large", "inline_leaf_tau_large",
                                                 "small_tasks_per_worker", "bucket_mode_max_leaf",
                                                 "stall_guard_us", "max_workers",
-                                                "leaf_filter_tau", "join_leaf_tau")]
+                                                "leaf_filter_tau", "join_leaf_tau",
+                                                "split_filter_tau")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -334,6 +338,15 @@ def deserialize(data: bytes) -> MPHF:
 
 def strerror(code: int) -> str:
     return _lib.rs_strerror(code).decode()
+
+
+def attempt_work(leaf_size: int, node_size: int, rotation: bool = True) -> float:
+    """Expected hash evaluations of one failed attempt at a node of node_size
+    keys when it stops at the first evidence that it fails (host only)."""
+    w = _lib.rs_attempt_work(leaf_size, node_size, RS_FLAG_ROTATION if rotation else 0)
+    if w < 0:
+        raise RecSplitError(-1, "rs_attempt_work")
+    return w
 
 
 def calibrate_valu() -> dict:

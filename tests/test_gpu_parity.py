@@ -158,19 +158,43 @@ def test_filtered_leaf_search(n, l, b, rot):
         rs().set_schedule(None)
 
 
-def test_early_exit_leaf_work_figure():
-    """The early-exit leaf work the library reports equals the closed form
-    summed over the oracle's leaf values."""
+SPLIT_FILTERED = [(20000, 12, 1000, True), (6000, 16, 2000, True), (4000, 10, 500, False),
+                  (3000, 8, 100, True), (2000, 18, 50, True), (5000, 6, 300, True),
+                  (3000, 13, 777, True)]
+
+
+@pytest.mark.parametrize("n,l,b,rot", SPLIT_FILTERED)
+def test_filtered_split_search(n, l, b, rot):
+    """Lower and upper split searches through the staged early-exit search
+    (split_filter_tau=1; chunk_shift 0 makes chunks long enough for it early),
+    with and without filtered leaves, then without: the oracle's bytes."""
+    keys = keygen.fingerprints(n, 700 + n + l)
+    try:
+        for sched in ({"split_filter_tau": 1, "chunk_shift_small": 0, "chunk_shift_large": 0},
+                      {"split_filter_tau": 1, "leaf_filter_tau": 1, "bucket_mode_max_leaf": 0},
+                      {"split_filter_tau": 0, "leaf_filter_tau": 0}):
+            rs().set_schedule(None)
+            rs().set_schedule(**sched)
+            _check_parity(keys, l, b, rot, str(sched))
+    finally:
+        rs().set_schedule(None)
+
+
+def test_early_exit_work_figures():
+    """The early-exit work the library reports equals the closed form summed
+    over the oracle's leaf values, and the per-size split table
+    (rs_attempt_work, pinned on the CPU) summed over its split values."""
     from closed_forms import leaf_early_exit_evals
 
-    for n, l, b, rot in ((20000, 12, 500, True), (20000, 8, 100, False), (4000, 16, 2000, True)):
+    for n, l, b, rot in ((20000, 12, 500, True), (20000, 8, 100, False), (4000, 16, 2000, True),
+                         (1500, 18, 300, True)):
         keys = keygen.fingerprints(n, 41)
         _case(f"early-exit work n={n} l={l} b={b} rot={rot}")
         data, _ = oracle.build(keys, l, b, rot)
         f = rs().build(keys, l, b, rot)
         nb = oracle.num_buckets(len(keys), b)
         sizes = np.bincount([oracle.bucket_of(int(w0), nb) for w0 in keys[:, 0]], minlength=nb)
-        want = 0.0
+        want, want_split = 0.0, 0.0
         for j in range(nb):
             vals = oracle.bucket_values(data, j)
             ms = oracle.preorder_sizes(int(sizes[j]), l)
@@ -179,9 +203,13 @@ def test_early_exit_leaf_work_figure():
                 if m <= l:
                     failed = int(v) // m if rot else int(v)
                     want += failed * leaf_early_exit_evals(m, rot) + m
-        got = f.stats()["early_exit_evals_leaf"]
-        assert got == pytest.approx(want, rel=2e-4), (l, b, rot)
-        assert got < f.stats()["useful_evals_leaf"]
+                else:
+                    want_split += int(v) * rs().attempt_work(l, m) + m
+        st = f.stats()
+        assert st["early_exit_evals_leaf"] == pytest.approx(want, rel=2e-4), (l, b, rot)
+        assert st["early_exit_evals_leaf"] < st["useful_evals_leaf"]
+        assert st["early_exit_evals_split"] == pytest.approx(want_split, rel=1e-5), (l, b, rot)
+        assert st["early_exit_evals_split"] <= st["useful_evals_split"]
 
 
 def test_serialise_roundtrip_and_corruption():
