@@ -176,6 +176,8 @@ def run_sweep(recsplit, keygen, torch, n=1_000_000, leaf_sizes=range(5, 17),
     keys = keygen.fingerprints_torch(n, 21, "cuda")
     torch.cuda.synchronize()
     recsplit.build(keys, 8, 100, True).free()
+    for l in leaf_sizes:  # the per-leaf-size tables, built once per process
+        recsplit.build(keys[:2000], l, 2000, True).free()
     rows = []
     for rot in (False, True):
         for l in leaf_sizes:
@@ -201,6 +203,9 @@ def run_single(recsplit, keygen, torch, l, b, n, seed=31):
     all keys form a permutation of [0, n)."""
     keys = keygen.fingerprints_torch(n, seed + l, "cuda")
     torch.cuda.synchronize()
+    # the per-leaf-size tables (node counts, Rice parameters, work model) are
+    # built once per process, at the first build with this leaf size
+    recsplit.build(keys[:64], l, b, True).free()
     t0 = time.perf_counter()
     f = recsplit.build(keys, l, b, True)
     dt = time.perf_counter() - t0

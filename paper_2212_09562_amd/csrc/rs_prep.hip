@@ -384,7 +384,8 @@ static double all_distinct(uint32_t j, uint32_t m) {
 // Poisson(t; m), T_j the Poisson(u_j) pmf truncated at u_j.  Parts other
 // than the last are all of one size, so their product is shared by the
 // node sizes with the same part count.  Long double: for m near 1300 the
-// pmfs reach e^-1300.  Fanout-2 splits are credited all m keys.
+// pmfs reach e^-1300.  Fanout-2 splits are credited all m keys.  About 60 ms
+// at l = 16 and 0.45 s at l = 24, once per process and leaf size.
 std::vector<double> split_work_table(uint32_t l) {
   const Shape s = make_shape(l);
   std::vector<double> w(kTable, 0.0);
