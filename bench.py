@@ -498,8 +498,14 @@ def main():
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "rs_filter_kernel", "ms_per_launch": ms_search,
                      "useful_hash_evals": evals, "attempt_hash_evals": attempt_evals(st),
+                     "work_unit": "hash evaluation; a failed attempt counts its expected "
+                                  "evaluations up to the first evidence of failure (leaf: a "
+                                  "collision within a class; lower/upper split: a child above "
+                                  "its part size), as the staged searches exploit; "
+                                  "attempt_hash_evals is the paper's count, m per attempt",
                      "ops_per_eval": OPS_PER_EVAL,
                      "hash_evals_per_s": evals_per_s,
+                     "attempt_hash_evals_per_s": attempt_evals(st) / (ms_search * 1e-3),
                      "calibrated_hash_loop_evals_per_s": rates["hash_evals"],
                      "frac_of_calibrated_hash_loop": evals_per_s / rates["hash_evals"],
                      "sustained_hash_loop_evals_per_s": rates["hash_evals_sustained"],
