@@ -681,16 +681,16 @@ __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)
 constexpr uint64_t kFound = 1ull << 63;
 __device__ __forceinline__ uint64_t cursor(uint64_t np) { return (np >> 32) & 0x7FFFFFFFull; }
 
-// Drop one in-flight chunk of task st; returns true for the one caller that
+// Drop n in-flight chunks of task st; returns true for the one caller that
 // must finalize (a value is known and nothing is in flight any more).
 // Relaxed agent-scope atomics on one cache line of the task state, performed
 // at the device coherence point; a caller that found a value waited for its
 // atomicMin and for the found bit before dropping its chunk, so whoever sees
 // the count reach zero with the bit set also sees the value.
-__device__ __forceinline__ bool release_chunk(TaskState* st) {
-  const uint64_t old =
-      __hip_atomic_fetch_add(&st->np, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if ((old & 0xFFFFFFFFull) != 1 || !(old & kFound)) return false;
+__device__ __forceinline__ bool release_chunk(TaskState* st, uint32_t n = 1) {
+  const uint64_t old = __hip_atomic_fetch_add(&st->np, 0ull - n, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+  if ((old & 0xFFFFFFFFull) != n || !(old & kFound)) return false;
   uint32_t expected = 0;
   return __hip_atomic_compare_exchange_strong(&st->closed, &expected, 1u, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -949,8 +949,8 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
       sh.fin = release_chunk(st) ? 1u : 0u;
       return false;
     }
-    // every worker may hold one claimed chunk whose result is not in yet
-    if (first * kWG >= c.cap + (uint64_t)P.workers * rmax * kWG) {
+    // every worker may hold two claimed chunks whose results are not in yet
+    if (first * kWG >= c.cap + 2ull * P.workers * rmax * kWG) {
       if (set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
         record_failure(P.ctl, t, slot, st, first);
       sh.fin = release_chunk(st) ? 1u : 0u;
@@ -988,9 +988,24 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
       r = r * 2 < rmax ? r * 2 : rmax;
     }
   }
+  // The owner claims its next chunk before evaluating the current one, so
+  // that the claim's round trip to the device coherence point overlaps the
+  // evaluation; it then holds two chunks in flight.  The next chunk lies
+  // above the current one, so a value found in the current chunk drops it
+  // unevaluated.  A helper, which may have to leave, holds one chunk only.
+  uint64_t next_old = 0;  // thread 0: the word the claim of the next chunk returned
+  uint32_t next_r = 0;
+  bool have_next = false;
   for (;;) {
     __syncthreads();  // thread 0's decision is visible
     if (!sh.go) break;
+    if (tid == 0 && own) {
+      next_r = r;
+      next_old = __hip_atomic_fetch_add(&st->np, ((uint64_t)r << 32) | 1ull, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+      have_next = true;
+      r = r * 2 < rmax ? r * 2 : rmax;
+    }
     if (leaf && filtered_leaf(P, tau))
       run_leaf_filtered(c, sh.first, sh.rounds, patience(c, tau), &sh.best);
     else if (split_filter && sh.rounds >= kMinFilterRounds)
@@ -1004,14 +1019,26 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
       sh.best = kInf;
       sh.fin = 0;
       sh.go = 0;
+      const uint32_t held = have_next ? 2u : 1u;
+      have_next = false;
       if (v != kInf) {
         __hip_atomic_fetch_min(&st->best, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wait_memory();  // the value is in before the found bit
         __hip_atomic_fetch_or(&st->np, kFound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wait_memory();  // and the bit before the chunk is dropped
-        sh.fin = release_chunk(st) ? 1u : 0u;
+        wait_memory();  // and the bit before the chunks are dropped
+        sh.fin = release_chunk(st, held) ? 1u : 0u;
       } else if (leave()) {
-        sh.fin = release_chunk(st) ? 1u : 0u;
+        sh.fin = release_chunk(st, held) ? 1u : 0u;
+      } else if (held == 2) {
+        if (next_old & kFound) {
+          // the next chunk lies above a known value: drop both
+          sh.fin = release_chunk(st, 2) ? 1u : 0u;
+        } else {
+          // drop the evaluated chunk (the next one keeps the count above
+          // zero, so this cannot be the last drop) and move on
+          __hip_atomic_fetch_add(&st->np, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sh.go = decide(next_old, next_r) ? 1u : 0u;
+        }
       } else {
         // drop the evaluated chunk and claim the next with one atomic
         sh.go = decide(__hip_atomic_fetch_add(&st->np, (uint64_t)r << 32, __ATOMIC_RELAXED,
