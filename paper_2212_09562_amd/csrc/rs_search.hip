@@ -708,6 +708,12 @@ struct Shared {
   uint32_t iter;
   uint64_t arg;
   int32_t pick;
+  // thread 0's state across tasks, kept in LDS rather than in registers that
+  // the task bodies need: the queue slot this worker has reserved, and the
+  // idle bookkeeping of the stall guard and the back-off
+  uint64_t my_q;
+  uint64_t last_finished, idle_since;
+  uint32_t idle;
 };
 
 __device__ __forceinline__ bool filtered_leaf(const SearchParams& P, uint32_t tau) {
@@ -920,7 +926,7 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
 // their registers.
 template <uint32_t kMode, bool kLeafTask>
 __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
-                            const JobDev& J, uint64_t slot, bool own, uint64_t& my_q) {
+                            const JobDev& J, uint64_t slot, bool own) {
   const uint32_t tid = threadIdx.x;
   constexpr bool leaf = kLeafTask;
   Node c = make_node(t, J, P.start, P.cap_shift);
@@ -973,7 +979,7 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
   // a helper leaves as soon as the queue slot it holds is ready
   auto leave = [&]() {
     return ld_relaxed(&P.ctl->error) != 0 ||
-           (!own && my_q < kExhausted && ld_relaxed(&P.ready[my_q]) != 0);
+           (!own && sh.my_q < kExhausted && ld_relaxed(&P.ready[sh.my_q]) != 0);
   };
   if (tid == 0) {
     sh.fin = 0;
@@ -992,14 +998,16 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
   // that the claim's round trip to the device coherence point overlaps the
   // evaluation; it then holds two chunks in flight.  The next chunk lies
   // above the current one, so a value found in the current chunk drops it
-  // unevaluated.  A helper, which may have to leave, holds one chunk only.
+  // unevaluated.  A helper, which may have to leave, holds one chunk only,
+  // and so does the filter kernel, where the extra state would spill
+  // registers to scratch memory.
   uint64_t next_old = 0;  // thread 0: the word the claim of the next chunk returned
   uint32_t next_r = 0;
   bool have_next = false;
   for (;;) {
     __syncthreads();  // thread 0's decision is visible
     if (!sh.go) break;
-    if (tid == 0 && own) {
+    if (tid == 0 && own && kMode == kSearchNode) {
       next_r = r;
       next_old = __hip_atomic_fetch_add(&st->np, ((uint64_t)r << 32) | 1ull, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
@@ -1090,7 +1098,7 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
 // queue; otherwise it joins another worker's search).
 template <uint32_t kMode>
 __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, uint64_t slot,
-                         bool own, uint64_t& my_q) {
+                         bool own) {
   Task t = sh.task;
   t.key_off = uni64(t.key_off);
   t.node = uni64(t.node);
@@ -1102,13 +1110,13 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
     run_bucket(P, sh, s_keys, t, J);
   } else {
     if (t.m > uni(J.l)) {
-      run_claimed<kMode, false>(P, sh, s_keys, t, J, slot, own, my_q);
+      run_claimed<kMode, false>(P, sh, s_keys, t, J, slot, own);
       return;
     }
     if constexpr (kMode == kSearchFilter) {
       // long leaves (what the filter kernel is chosen for) can be joined
       if (P.join_leaf_tau && uni((uint32_t)J.tau[t.m]) >= P.join_leaf_tau) {
-        run_claimed<kMode, true>(P, sh, s_keys, t, J, slot, own, my_q);
+        run_claimed<kMode, true>(P, sh, s_keys, t, J, slot, own);
         return;
       }
     }
@@ -1128,10 +1136,13 @@ __device__ __forceinline__ void search_main(const SearchParams& P) {
   const uint32_t tid = threadIdx.x;
   const uint32_t g = blockIdx.x;
   const uint64_t total = P.ctl->total;
-  uint64_t my_q = kNoSlot;  // thread 0 only
-  uint64_t last_finished = 0, idle_since = 0;
-  uint32_t idle = 0;  // thread 0: consecutive rounds without work
-  if (tid == 0) sh.iter = 0;
+  if (tid == 0) {
+    sh.iter = 0;
+    sh.my_q = kNoSlot;
+    sh.last_finished = 0;
+    sh.idle_since = 0;
+    sh.idle = 0;  // consecutive rounds without work
+  }
   __syncthreads();
   for (;;) {
     __syncthreads();  // every thread has read the previous decision
@@ -1140,16 +1151,16 @@ __device__ __forceinline__ void search_main(const SearchParams& P) {
       if (ld_relaxed(&P.ctl->error) != 0) {
         act = kActExit;
       } else {
-        if (my_q == kNoSlot) {
+        if (sh.my_q == kNoSlot) {
           const uint64_t q = __hip_atomic_fetch_add(&P.ctl->head, 1ull, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
-          my_q = q < total ? q : kExhausted;
+          sh.my_q = q < total ? q : kExhausted;
         }
-        if (my_q < kExhausted && ld_relaxed(&P.ready[my_q]) != 0) {
+        if (sh.my_q < kExhausted && ld_relaxed(&P.ready[sh.my_q]) != 0) {
           fence_acquire();
           act = kActOwn;
-          sh.arg = my_q;
-          my_q = kNoSlot;
+          sh.arg = sh.my_q;
+          sh.my_q = kNoSlot;
         } else if (ld_relaxed(&P.ctl->finished) >= total) {
           // every node is final (slots a worker still holds may never be
           // filled: inline leaves take none)
@@ -1203,16 +1214,16 @@ __device__ __forceinline__ void search_main(const SearchParams& P) {
         // bug guard: no node finished for stall_ticks of the 100 MHz clock
         const uint64_t fin = ld_relaxed(&P.ctl->finished);
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
-        if (fin != last_finished || idle_since == 0) {
-          last_finished = fin;
-          idle_since = now;
-        } else if (now - idle_since > P.stall_ticks) {
+        if (fin != sh.last_finished || sh.idle_since == 0) {
+          sh.last_finished = fin;
+          sh.idle_since = now;
+        } else if (now - sh.idle_since > P.stall_ticks) {
           set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
         }
         // back off while idle: 1, 2, 4, 8 sleeps of 16 x 64 cycles
-        const uint32_t naps = 1u << (idle < 3 ? idle : 3);
+        const uint32_t naps = 1u << (sh.idle < 3 ? sh.idle : 3);
         for (uint32_t i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(16);
-        ++idle;
+        ++sh.idle;
       }
       continue;
     }
@@ -1220,11 +1231,11 @@ __device__ __forceinline__ void search_main(const SearchParams& P) {
     if (tid == 0) {
       sh.task = P.tasks[slot];
       if (act == kActOwn) st_relaxed(&P.active[g], (int32_t)slot);
-      idle_since = 0;
-      idle = 0;
+      sh.idle_since = 0;
+      sh.idle = 0;
     }
     __syncthreads();
-    run_task<kMode>(P, sh, s_keys, slot, act == kActOwn, my_q);
+    run_task<kMode>(P, sh, s_keys, slot, act == kActOwn);
     if (tid == 0 && act == kActOwn) st_relaxed(&P.active[g], (int32_t)-1);
     __syncthreads();
   }
