@@ -203,10 +203,11 @@ void rs_server_destroy(rs_server *s);
  *   split_filter_tau: a lower or upper split search whose Rice parameter is
  *                   at least this drops an attempt once a child holds more
  *                   keys than its part size (0: never)
- *   join_leaf_tau:  in a small launch, a leaf whose Rice parameter is at
- *                   least this is searched in claimed chunks, as splits are,
- *                   so that idle workers join it (only together with the
- *                   leaf filter; 0: never; other leaves have one worker each)
+ *   join_leaf_tau:  in a small launch that runs the filtered searches
+ *                   (leaf_filter_tau or split_filter_tau in effect for some
+ *                   job), a leaf whose Rice parameter is at least this is
+ *                   searched in claimed chunks, as splits are, so that idle
+ *                   workers join it (0: never; other leaves have one worker)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
  * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
  */
