@@ -197,17 +197,17 @@ def run_sweep(recsplit, keygen, torch, n=1_000_000, leaf_sizes=range(5, 17),
     return {"n": n, "rows": rows}
 
 
-def run_single(recsplit, keygen, torch, l, b, n, seed=31):
+def run_single(recsplit, keygen, torch, l, b, n, seed=31, rotation=True):
     """One build of n keys (drawn on the device, seed `seed` + l) at leaf size
-    l and bucket size b with rotation fitting, plus a check that the ranks of
-    all keys form a permutation of [0, n)."""
+    l and bucket size b (rotation fitting, or brute-force leaves), plus a
+    check that the ranks of all keys form a permutation of [0, n)."""
     keys = keygen.fingerprints_torch(n, seed + l, "cuda")
     torch.cuda.synchronize()
     # the per-leaf-size tables (node counts, Rice parameters, work model) are
     # built once per process, at the first build with this leaf size
-    recsplit.build(keys[:64], l, b, True).free()
+    recsplit.build(keys[:64], l, b, rotation).free()
     t0 = time.perf_counter()
-    f = recsplit.build(keys, l, b, True)
+    f = recsplit.build(keys, l, b, rotation)
     dt = time.perf_counter() - t0
     st = f.stats()
     r = f.query(keys)
@@ -215,7 +215,9 @@ def run_single(recsplit, keygen, torch, l, b, n, seed=31):
     perm = bool(torch.equal(torch.sort(r)[0], torch.arange(n, device=r.device, dtype=r.dtype)))
     f.free()
     ev = algorithmic_evals(st)
-    return {"n": n, "leaf_size": l, "bucket_size": b, "seconds": dt, "ns_per_key": dt * 1e9 / n,
+    return {"n": n, "leaf_size": l, "bucket_size": b,
+            "leaf_method": "rotation" if rotation else "brute", "seconds": dt,
+            "ns_per_key": dt * 1e9 / n,
             "bits_per_key": st["bytes"] * 8 / n, "ms_search": st["ms_search"],
             "evals_per_key": ev / n, "attempt_evals_per_key": attempt_evals(st) / n,
             "hash_evals_per_s": ev / (st["ms_search"] * 1e-3),
@@ -420,6 +422,8 @@ def main():
     ap.add_argument("--single", nargs=3, type=int, metavar=("L", "B", "N"), action="append",
                     help="instead: one rotation-fitting build of N keys at leaf size L, bucket "
                          "size B (repeatable)")
+    ap.add_argument("--brute", action="store_true",
+                    help="with --single: brute-force leaves instead of rotation fitting")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the construction is not "
@@ -435,7 +439,8 @@ def main():
         return
     if args.single:
         for l, b, n in args.single:
-            print(json.dumps({"single": run_single(recsplit, keygen, torch, l, b, n)}), flush=True)
+            print(json.dumps({"single": run_single(recsplit, keygen, torch, l, b, n,
+                                                   rotation=not args.brute)}), flush=True)
         return
 
     l, b, rot = WORKLOAD["leaf_size"], WORKLOAD["bucket_size"], WORKLOAD["rotation"]
