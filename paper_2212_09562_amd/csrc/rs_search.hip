@@ -283,7 +283,7 @@ __device__ void eval_chunk(const uint64_t* keys, const Node& c, uint64_t first, 
 }
 
 // The dynamic LDS of a worker (node mode: the staged keys of the current
-// task; for a filtered leaf also its queues).
+// task, then the queues of a filtered search).
 extern __shared__ uint64_t g_lds[];
 
 // ---------------------------------------------------------------- filtered leaves
@@ -720,7 +720,7 @@ __device__ __forceinline__ bool filtered_leaf(const SearchParams& P, uint32_t ta
   return P.leaf_filter_tau && P.stage_cap >= kLeafFilterWords && tau >= P.leaf_filter_tau;
 }
 
-// Rounds a filter queue waits: 1/32 of the leaf's expected rounds (about 2^tau
+// Rounds a filter queue waits: 1/32 of the node's expected rounds (about 2^tau
 // values, mult per attempt), 1 to 16.
 __device__ __forceinline__ uint32_t patience(const Node& c, uint32_t tau) {
   const uint64_t expect = (1ull << (tau < 40 ? tau : 40)) / ((uint64_t)c.mult * kWG);
@@ -730,9 +730,10 @@ __device__ __forceinline__ uint32_t patience(const Node& c, uint32_t tau) {
 
 // Most leaves are short and there are many: one worker searches such a leaf
 // alone, as one chunk without a bound on its rounds, with no global traffic
-// until the value is known (its state is never claimed).  Leaves whose Rice
-// parameter reaches join_leaf_tau go through the claimed chunks of run_task
-// instead, so that idle workers can join them.
+// until the value is known (its state is never claimed).  In small launches
+// of the filter kernel, leaves whose Rice parameter reaches join_leaf_tau go
+// through the claimed chunks of run_claimed instead, so that idle workers can
+// join them.
 template <bool kFilter>
 __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
                          const JobDev& J, uint64_t slot) {
@@ -920,7 +921,7 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
 
 // Search task t (queue slot `slot`) in claimed chunks until this worker's
 // claim is refused, and finalize it if this worker drops the last chunk in
-// flight.  my_q (thread 0 only) is the queue slot this worker has reserved; a
+// flight.  sh.my_q (thread 0) is the queue slot this worker has reserved; a
 // helper leaves as soon as that slot is ready.  kLeafTask: a long leaf (the
 // filter kernel only), instantiated apart so that the split searches keep
 // their registers.
