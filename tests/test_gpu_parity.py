@@ -160,14 +160,16 @@ def test_filtered_leaf_search(n, l, b, rot):
 
 SPLIT_FILTERED = [(20000, 12, 1000, True), (6000, 16, 2000, True), (4000, 10, 500, False),
                   (3000, 8, 100, True), (2000, 18, 50, True), (5000, 6, 300, True),
-                  (3000, 13, 777, True)]
+                  (3000, 13, 777, True), (600, 20, 100, True), (150, 22, 150, True)]
 
 
 @pytest.mark.parametrize("n,l,b,rot", SPLIT_FILTERED)
 def test_filtered_split_search(n, l, b, rot):
     """Lower and upper split searches through the staged early-exit search
-    (split_filter_tau=1; chunk_shift 0 makes chunks long enough for it early),
-    with and without filtered leaves, then without: the oracle's bytes."""
+    (split_filter_tau=1; chunk_shift 0 makes chunks long enough for it early;
+    at leaf sizes 20 and 22 the counter fields need more than 32 bits and the
+    splits keep the plain rounds), with and without filtered leaves, then
+    without: the oracle's bytes."""
     keys = keygen.fingerprints(n, 700 + n + l)
     try:
         for sched in ({"split_filter_tau": 1, "chunk_shift_small": 0, "chunk_shift_large": 0},
