@@ -8,9 +8,12 @@ fingerprints that are resident in HBM before the timed region starts.
 
 Prints one JSON line.  `roofline` prices the seed-search kernel (the
 dominant one) on the integer-VALU roofline: achieved = useful hash
-evaluations (those the sequential definition performs, a function of the
-chosen seeds) x 19 VALU instructions per evaluation / search-kernel time
-(HIP events on the kernel's stream); peak = 256 CU x 64 lanes x 2.4 GHz.
+evaluations x 19 VALU instructions per evaluation / search-kernel time (HIP
+events on the kernel's stream); peak = 256 CU x 64 lanes x 2.4 GHz.  Useful
+evaluations are a function of the chosen seeds: per node, m for the valid
+attempt and, per failed attempt, the expected evaluations until the first
+evidence of failure (the minimum a search that stops there needs; the
+paper's m per attempt is reported beside it).
 Beside it: the library's live calibration of the same instruction sequence
 with the keys in registers and no memory traffic.  `cpu_baseline` is the
 CPU oracle timed on a bounded sample of the same key set, bucket-sharded over
