@@ -164,7 +164,9 @@ int rs_server_submit(rs_server *s, const rs_job *job, uint64_t *ticket);
  * ends) returns RS_OK, sets *status to the build's code and *out to its
  * structure (NULL when the build failed; the caller releases it with
  * rs_free), fills *times when times is not NULL, and forgets the ticket.
- * RS_ERR_INVALID_ARG for an unknown or already collected ticket.
+ * RS_ERR_INVALID_ARG for an unknown or already collected ticket; when
+ * several threads poll one ticket, exactly one of them collects it and the
+ * others (blocked ones included) get RS_ERR_INVALID_ARG.
  */
 int rs_server_poll(rs_server *s, uint64_t ticket, int wait, rs_mphf **out, int *status,
                    rs_request_times *times);

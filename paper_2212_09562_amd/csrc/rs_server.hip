@@ -310,10 +310,17 @@ int rs_server_poll(rs_server* S, uint64_t ticket, int wait, rs_mphf** out, int* 
                    rs_request_times* times) {
   if (!S || !out || !status) return RS_ERR_INVALID_ARG;
   std::unique_lock<std::mutex> lock(S->mu);
-  auto it = S->reqs.find(ticket);
-  if (it == S->reqs.end()) return RS_ERR_INVALID_ARG;
+  if (S->reqs.find(ticket) == S->reqs.end()) return RS_ERR_INVALID_ARG;
+  // Another thread polling the same ticket may collect (and erase) it while
+  // this one waits, so the entry is looked up again after every wake-up
+  // instead of holding an iterator across the wait.
   if (wait)
-    S->cv_done.wait(lock, [&] { return it->second.status != RS_PENDING; });
+    S->cv_done.wait(lock, [&] {
+      auto w = S->reqs.find(ticket);
+      return w == S->reqs.end() || w->second.status != RS_PENDING;
+    });
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return RS_ERR_INVALID_ARG;  // collected by another poll
   Request& r = it->second;
   if (r.status == RS_PENDING) return RS_PENDING;
   *out = r.out;

@@ -173,6 +173,21 @@ def _keys_arg(keys):
     return keys.data_ptr() if keys.numel() else None, keys.shape[0], RS_FLAG_KEYS_ON_DEVICE, keys
 
 
+def _check_out(out, n: int, device):
+    """The query kernel writes n 64-bit words through out's pointer: it must be
+    a contiguous tensor of 8-byte elements on the keys' device with room for n."""
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("out must be a torch tensor")
+    if out.device != device:
+        raise ValueError(f"out is on {out.device}, the keys on {device}")
+    if out.element_size() != 8 or out.is_floating_point() or out.is_complex():
+        raise ValueError("out must hold 64-bit integers")
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    if out.numel() < n:
+        raise ValueError(f"out holds {out.numel()} elements, {n} are needed")
+
+
 class MPHF:
     """A built (or deserialised) minimal perfect hash function."""
 
@@ -198,8 +213,12 @@ class MPHF:
         if flags & RS_FLAG_KEYS_ON_DEVICE:
             if out is None:
                 out = torch.empty(n, dtype=torch.int64, device=keys.device)
+            else:
+                _check_out(out, n, keys.device)
             _check(_lib.rs_query(self._h, ptr, n, out.data_ptr() if n else None, flags), "rs_query")
             return out
+        if out is not None:
+            raise ValueError("out is for device keys only; host queries return a new array")
         res = np.zeros(n, dtype=np.uint64)
         _check(_lib.rs_query(self._h, ptr, n, res.ctypes.data if n else None, 0), "rs_query")
         return res

@@ -111,3 +111,24 @@ def test_schedule_defaults_and_validation():
     assert recsplit.get_schedule() == d
     assert recsplit.set_schedule(chunk_shift_large=7)["chunk_shift_large"] == 7
     assert recsplit.set_schedule(None) == d
+
+
+def test_query_output_tensor_checked_before_the_library_is_called():
+    """A caller-supplied out tensor that is short, of the wrong element size,
+    non-contiguous or on another device would let the query kernel write out
+    of bounds: the binding refuses it first."""
+    import torch
+
+    from paper_2212_09562_amd import recsplit
+
+    cpu = torch.device("cpu")
+    recsplit._check_out(torch.empty(10, dtype=torch.int64), 10, cpu)
+    bad = [(torch.empty(9, dtype=torch.int64), ValueError),
+           (torch.empty(10, dtype=torch.int32), ValueError),
+           (torch.empty(10, dtype=torch.float64), ValueError),
+           (torch.empty(20, dtype=torch.int64)[::2], ValueError),
+           (torch.empty(10, dtype=torch.int64, device="meta"), ValueError),
+           ([0] * 10, TypeError)]
+    for out, exc in bad:
+        with pytest.raises(exc):
+            recsplit._check_out(out, 10, cpu)
