@@ -83,6 +83,7 @@ def lib():
                                        _u64p, u64, _u64p, _u64p, ctypes.POINTER(_Stats)]),
             "or_query": (i32, [_u8p, u64, _u64p, u64, _u64p]),
             "or_bucket_values": (i32, [_u8p, u64, u64, _u64p, u64, _u64p]),
+            "or_bucket_record": (i32, [_u8p, u64, u64, _u64p, u64, _u64p]),
             "or_free": (None, [ctypes.c_void_p]),
         }
         for name, (res, args) in sig.items():
@@ -265,3 +266,18 @@ def bucket_values(data: bytes, bucket: int) -> np.ndarray:
     if rc:
         raise OracleError(rc, "bucket_values")
     return out[:cnt.value].copy()
+
+
+def bucket_record(data: bytes, bucket: int) -> tuple:
+    """(record words, record bits) of one bucket, read out of serialised
+    bytes and repacked from bit 0 (zero padded), comparable word for word
+    with the records of build_buckets."""
+    buf = np.frombuffer(data, dtype=np.uint8).copy()
+    cap = 1 << 16
+    out = np.zeros(cap, dtype=np.uint64)
+    nbits = ctypes.c_uint64()
+    rc = lib().or_bucket_record(buf.ctypes.data_as(_u8p), len(buf), bucket, _p64(out), cap,
+                                ctypes.byref(nbits))
+    if rc:
+        raise OracleError(rc, "bucket_record")
+    return out[:(nbits.value + 63) // 64].copy(), int(nbits.value)

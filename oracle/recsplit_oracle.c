@@ -784,7 +784,7 @@ int or_build_buckets(const uint64_t *keys, uint64_t n, uint32_t l, uint32_t b, u
       rc = OR_ERR_INVALID_ARG;
       break;
     }
-    memcpy(vals + vused, nd.val, nd.len * sizeof(uint64_t));
+    if (nd.len) memcpy(vals + vused, nd.val, nd.len * sizeof(uint64_t)); /* empty: val may be NULL */
     vused += nd.len;
     counts[i] = nd.len;
     or_bits gr = {0};
@@ -873,6 +873,10 @@ static int or_view_open(const uint8_t *bytes, uint64_t len, or_view *v) {
   v->gr = w + at + 2;
   if (v->C[0] != 0 || v->C[v->nb] != v->n || v->P[0] != 0 || v->P[v->nb] != v->gr_bits)
     return OR_ERR_CORRUPT;
+  /* both sequences are prefix sums: non-decreasing, so no bucket claims
+   * more keys or record bits than the whole structure holds */
+  for (uint64_t j = 0; j < v->nb; ++j)
+    if (v->C[j + 1] < v->C[j] || v->P[j + 1] < v->P[j]) return OR_ERR_CORRUPT;
   return OR_OK;
 }
 
@@ -958,6 +962,32 @@ int or_bucket_values(const uint8_t *bytes, uint64_t len, uint64_t j, uint64_t *o
   }
   free(val);
   free(sz);
+  or_view_close(&v);
+  return rc;
+}
+
+/* The Golomb-Rice record of bucket j as stored in serialised bytes: the bits
+ * [P_j, P_j+1) of the record vector, repacked from bit 0 of out (words
+ * zero-padded), so that it can be compared word for word with a record the
+ * oracle builds itself (or_build_buckets).  Reads only; no arithmetic of the
+ * method. */
+int or_bucket_record(const uint8_t *bytes, uint64_t len, uint64_t j, uint64_t *out, uint64_t cap,
+                     uint64_t *nbits) {
+  or_view v;
+  int rc = or_view_open(bytes, len, &v);
+  if (rc == OR_OK && j >= v.nb) rc = OR_ERR_INVALID_ARG;
+  if (rc == OR_OK) {
+    uint64_t lo = v.P[j], bits = v.P[j + 1] - v.P[j];
+    uint64_t nw = (bits + 63) / 64;
+    if (nw > cap) rc = OR_ERR_INVALID_ARG;
+    else {
+      for (uint64_t i = 0; i < nw; ++i) {
+        uint32_t take = bits - 64 * i < 64 ? (uint32_t)(bits - 64 * i) : 64u;
+        out[i] = or_bits_get(v.gr, lo + 64 * i, take);
+      }
+      *nbits = bits;
+    }
+  }
   or_view_close(&v);
   return rc;
 }

@@ -159,6 +159,48 @@ def test_worked_example_split_with_singleton():
     assert _is_perm(oracle.query(data, k), 9)
 
 
+def test_worked_example_record_layout_with_rice_parameters():
+    """A bucket of 16 keys at l = 8: a lower split into two leaves of 8, three
+    nodes with Rice parameters 2, 8, 8.  The record is laid out here by hand
+    from Sec. 2.2 "Representation" (reading R18): the fixed parts of all
+    three values in preorder, then their three unary parts in preorder (q
+    zeros, then a one).  A record that interleaves the two parts per node,
+    orders the nodes otherwise or writes a fixed part most significant bit
+    first differs from this one."""
+    k = keygen.fingerprints(16, 2031)
+    l = 8
+    data, st = oracle.build(k, l, 16, True)
+    assert st["nodes_split"] == 1 and st["nodes_leaf"] == 2
+    assert oracle.preorder_sizes(16, l) == [16, 8, 8]
+    taus = [oracle.tau(16, l), oracle.tau(8, l), oracle.tau(8, l)]
+    assert taus == [2, 8, 8]
+    # the split seed, then the children as the definition assigns them
+    # (child = floor(remap(h, 16) / 8), keys kept in input order)
+    w1 = k[:, 1]
+    s = oracle.split_search(w1, l, 0)
+    x = s + oracle.start_seed(0)
+    child = [(((oracle.hash64(int(w), x) >> 32) * 16) >> 32) // 8 for w in w1]
+    vals = [s]
+    for c in (0, 1):
+        sel = [i for i in range(16) if child[i] == c]
+        assert len(sel) == 8
+        v, _ = oracle.leaf_search(w1[sel], (k[sel, 0] & np.uint64(1)).astype(np.uint8), 1,
+                                  oracle.LEAF_ROT)
+        vals.append(v)
+    assert list(oracle.bucket_values(data, 0)) == vals
+    want = []
+    for v, t in zip(vals, taus):  # fixed parts, low bit first
+        want += [(v >> i) & 1 for i in range(t)]
+    for v, t in zip(vals, taus):  # unary parts
+        want += [0] * (v >> t) + [1]
+    assert all(v >> t > 0 for v, t in zip(vals, taus)), "every unary part non-empty"
+    words, nbits = oracle.bucket_record(data, 0)
+    assert nbits == len(want)
+    assert _bits(words, 0, nbits) == want
+    hdr, _, gr_bits, gr = _parse(data)
+    assert gr_bits == len(want) and _bits(gr, 0, gr_bits) == want
+
+
 def test_record_roundtrip_and_layout():
     """Values decoded from the bytes equal the values the build chose, and the
     Golomb-Rice vector is the concatenation of the per-bucket records."""
