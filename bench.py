@@ -9,15 +9,21 @@ fingerprints that are resident in HBM before the timed region starts.
 Prints one JSON line.  `roofline` prices the seed-search kernel (the
 dominant one) on the integer-VALU roofline: achieved = useful hash
 evaluations x 19 VALU instructions per evaluation / search-kernel time (HIP
-events on the kernel's stream); peak = 256 CU x 64 lanes x 2.4 GHz.  Useful
-evaluations are a function of the chosen seeds: per node, m for the valid
-attempt and, per failed attempt, the expected evaluations until the first
-evidence of failure (the minimum a search that stops there needs; the
-paper's m per attempt is reported beside it).
-Beside it: the library's live calibration of the same instruction sequence
-with the keys in registers and no memory traffic.  `cpu_baseline` is the
-CPU oracle timed on a bounded sample of the same key set, bucket-sharded over
-the host's cores (one single-threaded process per core).
+events on the kernel's stream); peak = the same 19-instruction sequence run
+by the library's calibration kernel in this process (keys in registers, no
+memory, full occupancy, about two seconds), x 19 -- its counters show one
+wave instruction per 4 cycles per SIMD at the clock the chip holds, i.e. the
+nominal 256 CU x 64 lanes per cycle; the nominal figure at 2.4 GHz is
+reported beside it.  Useful evaluations are a function of the chosen seeds:
+per node, m for the valid attempt and, per failed attempt, the expected
+evaluations until the first evidence of failure (the minimum a search that
+stops there needs; the paper's m per attempt is reported beside it).
+`cpu_baseline` is the CPU oracle timed on a bounded sample of the same key
+set, bucket-sharded over the host's cores (one single-threaded process per
+core), and compared bucket by bucket with the last timed build.  The
+plain-RecSplit (10^5 keys) and rotation-fitting (10^6 keys) workloads at
+l = 8, b = 100 follow, each with its own roofline figure and one-core oracle
+time, then the batched and served forms.
 """
 from __future__ import annotations
 
@@ -102,41 +108,16 @@ def measured_traffic():
         return None
 
 
-_CPU_SHARD = """
-import json, sys, time
-import numpy as np
-sys.path.insert(0, sys.argv[1])
-import oracle
-keys = np.load(sys.argv[2])
-first, count, l, b = (int(x) for x in sys.argv[3:7])
-t0 = time.perf_counter()
-recs, st = oracle.build_buckets(keys, l, b, True, list(range(first, first + count)))
-dt = time.perf_counter() - t0
-print(json.dumps({"keys": sum(r[1] for r in recs), "seconds": dt,
-                  "evals": st["evals_split"] + st["evals_leaf"]}))
-"""
-
-
-def cpu_baseline(keys, l, b, per_core, cores):
+def cpu_baseline(keys, l, b, per_core, cores, gpu_bytes=None):
     """The CPU oracle on the first per_core * cores buckets of the same key
     set, bucket-sharded over `cores` single-threaded processes (each
-    buckets all keys, then builds its buckets)."""
-    import subprocess
-    import tempfile
+    buckets all keys, then builds its buckets).  With gpu_bytes (the
+    serialised structure of a timed GPU build of the same keys), every
+    oracle bucket is also compared with it: node values decoded from the GPU
+    bytes and the bucket's Golomb-Rice record, bit for bit."""
+    from oracle import bucket_record, bucket_values, shards
 
-    with tempfile.TemporaryDirectory() as tmp:
-        path = os.path.join(tmp, "keys.npy")
-        np.save(path, np.ascontiguousarray(keys))
-        env = dict(os.environ, OMP_NUM_THREADS="1")
-        t0 = time.perf_counter()
-        procs = [subprocess.Popen([sys.executable, "-c", _CPU_SHARD, ROOT, path, str(i * per_core),
-                                   str(per_core), str(l), str(b)],
-                                  stdout=subprocess.PIPE, text=True, env=env)
-                 for i in range(cores)]
-        outs = [json.loads(p.communicate()[0].strip().splitlines()[-1]) for p in procs]
-        wall = time.perf_counter() - t0
-        if any(p.returncode for p in procs):
-            raise RuntimeError("oracle shard failed")
+    res, outs, wall = shards.timed_shards(keys, l, b, True, per_core, cores)
     nkeys = sum(o["keys"] for o in outs)
     slowest = max(o["seconds"] for o in outs)
     model = ""
@@ -145,16 +126,26 @@ def cpu_baseline(keys, l, b, per_core, cores):
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": nkeys / slowest, "unit": "keys/s", "cores": cores, "kind": "oracle",
-            "cpu_model": model, "host_cpus": os.cpu_count(),
-            "core_seconds": sum(o["seconds"] for o in outs),
-            "sample": f"buckets 0..{per_core * cores - 1} ({nkeys} keys) of the same "
-                      f"{len(keys)}-key set, {cores} single-threaded oracle processes of "
-                      f"{per_core} buckets each (each also buckets all keys); value = keys / "
-                      f"slowest process time",
-            "seconds": slowest, "wall_seconds_incl_startup": wall,
-            "per_core_keys_per_s": nkeys / sum(o["seconds"] for o in outs),
-            "attempt_evals_per_s": sum(o["evals"] for o in outs) / slowest}
+    out = {"value": nkeys / slowest, "unit": "keys/s", "cores": cores, "kind": "oracle",
+           "cpu_model": model, "host_cpus": os.cpu_count(),
+           "core_seconds": sum(o["seconds"] for o in outs),
+           "sample": f"buckets 0..{per_core * cores - 1} ({nkeys} keys) of the same "
+                     f"{len(keys)}-key set, {cores} single-threaded oracle processes of "
+                     f"{per_core} buckets each (each also buckets all keys); value = keys / "
+                     f"slowest process time",
+           "seconds": slowest, "wall_seconds_incl_startup": wall,
+           "per_core_keys_per_s": nkeys / sum(o["seconds"] for o in outs),
+           "attempt_evals_per_s": sum(o["evals"] for o in outs) / slowest}
+    if gpu_bytes is not None:
+        bad = []
+        for j, (size, vals, words, bits) in sorted(res.items()):
+            gw, gb = bucket_record(gpu_bytes, j)
+            if (not np.array_equal(bucket_values(gpu_bytes, j), vals) or gb != bits
+                    or not np.array_equal(gw, words)):
+                bad.append(j)
+        out["parity_buckets_checked"] = len(res)
+        out["parity_buckets_differing"] = bad
+    return out
 
 
 def run_query(f, dev, torch, reps=5):
@@ -227,14 +218,72 @@ def run_single(recsplit, keygen, torch, l, b, n, seed=31, rotation=True):
             "ranks_are_permutation": perm}
 
 
-def _search_roofline(evals, ms_search):
+SMALL_CONFIGS = [
+    # (name, n, seed, rotation): l = 8, b = 100, the plain-RecSplit and the
+    # rotation-fitting parity workloads
+    ("plain_l8_b100_n1e5", 100_000, 1, False),
+    ("rotation_l8_b100_n1e6", 1_000_000, 2, True),
+]
+
+
+def run_small_config(recsplit, keygen, torch, n, seed, rotation, rates, reps=7):
+    """One small-leaf workload (l = 8, b = 100): whole builds from device
+    keys (median of `reps`), the search kernel priced on the same roofline
+    as the headline, and the oracle on one host core building the same set,
+    whose bytes must equal the GPU's."""
+    import oracle
+
+    l, b = 8, 100
+    keys = keygen.fingerprints(n, seed)
+    dev = torch.from_numpy(keys.view(np.int64)).cuda()
+    torch.cuda.synchronize()
+    recsplit.build(dev, l, b, rotation).free()
+    times, stats = [], []
+    f = None
+    for _ in range(reps):
+        if f is not None:
+            f.free()
+        t0 = time.perf_counter()
+        f = recsplit.build(dev, l, b, rotation)
+        times.append(time.perf_counter() - t0)
+        stats.append(f.stats())
+    gpu_bytes = f.serialize()
+    f.free()
+    med = sorted(times)[len(times) // 2]
+    st = stats[-1]
+    evals = algorithmic_evals(st)
+    ms_search = sorted(x["ms_search"] for x in stats)[len(stats) // 2]
+    t0 = time.perf_counter()
+    want, _ = oracle.build(keys, l, b, rotation)
+    t_oracle = time.perf_counter() - t0
+    out = {"n": n, "leaf_size": l, "bucket_size": b,
+           "leaf_method": "rotation" if rotation else "brute",
+           "keys_per_s": n / med, "ms_per_build_median": med * 1e3,
+           "stage_ms": {k: sorted(x[k] for x in stats)[len(stats) // 2]
+                        for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},
+           "bits_per_key": st["bytes"] * 8 / n,
+           "search": _search_roofline(evals, ms_search, rates),
+           "identical_to_oracle": gpu_bytes == want,
+           "cpu_baseline": {"value": n / t_oracle, "unit": "keys/s", "cores": 1,
+                            "kind": "oracle", "seconds": t_oracle,
+                            "sample": f"the whole {n}-key set, one single-threaded oracle call"}}
+    return out
+
+
+def _search_roofline(evals, ms_search, rates=None):
+    """The search kernel on the headline's roofline: useful evaluations x 19
+    against the sustained rate of the 19-instruction sequence (rates from
+    rs_calibrate_valu), and against the nominal peak."""
     evals_per_s = evals / (ms_search * 1e-3)
     achieved = evals_per_s * OPS_PER_EVAL / 1e12
-    return {"hash_evals_per_s": evals_per_s, "achieved_tops": achieved,
-            "frac": achieved / (PEAK_LANE_OPS / 1e12), "ms_search": ms_search}
+    out = {"hash_evals_per_s": evals_per_s, "achieved_tops": achieved,
+           "frac_nominal": achieved / (PEAK_LANE_OPS / 1e12), "ms_search": ms_search}
+    if rates:
+        out["frac"] = evals_per_s / rates["hash_evals_sustained"]
+    return out
 
 
-def run_batched(recsplit, keygen, torch, steps, warmup):
+def run_batched(recsplit, keygen, torch, steps, warmup, rates=None):
     """64 independent key sets (sizes log-uniform in [10^3, 10^6], l in
     {8, 12, 16}, b in {100, 500, 2000}, seed 4), device resident: one
     rs_build_batch call (one persistent search launch for all sets) against
@@ -275,7 +324,7 @@ def run_batched(recsplit, keygen, torch, steps, warmup):
             "plain_keys_per_s": total / t_plain, "speedup_vs_plain": t_plain / t_batch,
             "ms_batched": t_batch * 1e3, "ms_plain": t_plain * 1e3,
             "identical_to_plain": same, "useful_hash_evals": evals,
-            "search": _search_roofline(evals, stats[0]["ms_search"])}
+            "search": _search_roofline(evals, stats[0]["ms_search"], rates)}
 
 
 def _pct(xs, q):
@@ -425,6 +474,12 @@ def main():
     ap.add_argument("--single", nargs=3, type=int, metavar=("L", "B", "N"), action="append",
                     help="instead: one rotation-fitting build of N keys at leaf size L, bucket "
                          "size B (repeatable)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="instead: only the VALU issue-rate calibration (for counter runs)")
+    ap.add_argument("--rotation-lookup", action="store_true",
+                    help="rotation leaves of at most 16 keys find their rotation by table lookups")
+    ap.add_argument("--schedule", default="",
+                    help="search schedule changes, e.g. max_workers=250,bucket_wave=0")
     ap.add_argument("--brute", action="store_true",
                     help="with --single: brute-force leaves instead of rotation fitting")
     args = ap.parse_args()
@@ -437,8 +492,16 @@ def main():
 
     from paper_2212_09562_amd import keygen, recsplit
 
+    if args.rotation_lookup:
+        recsplit.set_schedule(rotation_lookup=1)
+    if args.schedule:
+        recsplit.set_schedule(**{k: int(v) for k, v in
+                                 (kv.split("=") for kv in args.schedule.split(","))})
     if args.sweep:
         print(json.dumps({"sweep": run_sweep(recsplit, keygen, torch)}), flush=True)
+        return
+    if args.calibrate:
+        print(json.dumps({"valu_rates": recsplit.calibrate_valu()}), flush=True)
         return
     if args.single:
         for l, b, n in args.single:
@@ -477,13 +540,17 @@ def main():
     t1 = time.perf_counter()
     secs = t1 - t0
     query = run_query(f, dev, torch)
+    gpu_bytes = f.serialize()
     f.free()
     st = stats[-1]
     evals = algorithmic_evals(st)
     ms_search = sum(s["ms_search"] for s in stats) / len(stats)
     evals_per_s = evals / (ms_search * 1e-3)
     achieved = evals_per_s * OPS_PER_EVAL / 1e12
-    peak = PEAK_LANE_OPS / 1e12
+    # the ceiling: the same 19-instruction evaluation sequence with its keys
+    # in registers, no memory and full occupancy, run for about two seconds
+    # in this process (the clock the chip holds under sustained integer load)
+    peak = rates["hash_evals_sustained"] * OPS_PER_EVAL / 1e12
     traffic = measured_traffic()
     out = {
         "metric": METRIC,
@@ -504,6 +571,14 @@ def main():
                    "global_batch": n, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                      "frac": achieved / peak, "traffic": traffic,
+                     "peak_source": "measured in this run: the 19-instruction evaluation "
+                                    "sequence (rs_calibrate_valu, keys in registers, 8 waves "
+                                    "per SIMD, about 2 s) at its sustained rate, x 19; its "
+                                    "counters show one wave instruction per 4 cycles per SIMD",
+                     "peak_nominal": PEAK_LANE_OPS / 1e12,
+                     "frac_nominal": achieved / (PEAK_LANE_OPS / 1e12),
+                     "frac_attempt_unit": attempt_evals(st) / (ms_search * 1e-3)
+                                          / rates["hash_evals_sustained"],
                      "kernel": "rs_filter_kernel", "ms_per_launch": ms_search,
                      "useful_hash_evals": evals, "attempt_hash_evals": attempt_evals(st),
                      "work_unit": "hash evaluation; a failed attempt counts its expected "
@@ -515,9 +590,7 @@ def main():
                      "hash_evals_per_s": evals_per_s,
                      "attempt_hash_evals_per_s": attempt_evals(st) / (ms_search * 1e-3),
                      "calibrated_hash_loop_evals_per_s": rates["hash_evals"],
-                     "frac_of_calibrated_hash_loop": evals_per_s / rates["hash_evals"],
-                     "sustained_hash_loop_evals_per_s": rates["hash_evals_sustained"],
-                     "frac_of_sustained_hash_loop": evals_per_s / rates["hash_evals_sustained"]},
+                     "sustained_hash_loop_evals_per_s": rates["hash_evals_sustained"]},
         "bits_per_key": st["bytes"] * 8 / n,
         "query": query,
         "stage_ms": {k: sum(s[k] for s in stats) / len(stats)
@@ -530,8 +603,13 @@ def main():
     recsplit.build(keys, l, b, rot).free()
     out["host_keys_keys_per_s"] = n / (time.perf_counter() - t0)
     if not args.headline_only:
+        out["small_configs"] = {}
+        for name, sn, seed, srot in SMALL_CONFIGS:
+            print(f"[bench] {name}", file=sys.stderr, flush=True)
+            out["small_configs"][name] = run_small_config(recsplit, keygen, torch, sn, seed, srot,
+                                                          rates)
         print("[bench] batched workload", file=sys.stderr, flush=True)
-        out["batched"] = run_batched(recsplit, keygen, torch, max(1, args.steps), 1)
+        out["batched"] = run_batched(recsplit, keygen, torch, max(1, args.steps), 1, rates)
         print("[bench] served workload", file=sys.stderr, flush=True)
         out["served"] = run_served(recsplit, keygen, torch, args.served_requests,
                                    args.budget_gib, args.slots, args.per_launch,
@@ -539,7 +617,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
-        out["cpu_baseline"] = cpu_baseline(keys, l, b, args.cpu_buckets, cores)
+        out["cpu_baseline"] = cpu_baseline(keys, l, b, args.cpu_buckets, cores, gpu_bytes)
     print(json.dumps(out), flush=True)
 
 

@@ -210,6 +210,14 @@ void rs_server_destroy(rs_server *s);
  *                   job), a leaf whose Rice parameter is at least this is
  *                   searched in claimed chunks, as splits are, so that idle
  *                   workers join it (0: never; other leaves have one worker)
+ *   rotation_lookup: rotation-fitting leaves of at most 16 keys find the
+ *                   rotation of a candidate hash function by two table
+ *                   lookups (Sec. 4 "Lookup Tables") instead of the wave
+ *                   testing every rotation (0: off; the filter kernel that
+ *                   long searches use keeps the wave test)
+ *   bucket_wave:    in whole-bucket mode, each wave builds its own bucket
+ *                   trees, 64 attempts a round (1), or four waves share each
+ *                   bucket, 256 attempts a round (0)
  * Process-wide; builds started afterwards use it.  rs_set_schedule(NULL)
  * restores the defaults; RS_ERR_INVALID_ARG for a value out of range.
  */
@@ -223,6 +231,8 @@ typedef struct {
   uint32_t leaf_filter_tau;
   uint32_t join_leaf_tau;
   uint32_t split_filter_tau;
+  uint32_t rotation_lookup;
+  uint32_t bucket_wave;
 } rs_schedule;
 
 int rs_set_schedule(const rs_schedule *s);
@@ -240,12 +250,23 @@ int rs_query(const rs_mphf *f, const rs_key128 *keys, uint64_t n, uint64_t *out,
 /*
  * Serialised bytes (little-endian 64-bit words): header, Elias-Fano sequence
  * of the bucket prefix sums, Elias-Fano sequence of the record bit offsets,
- * Golomb-Rice bit vector.  *bytes stays valid until rs_free(f).
+ * Golomb-Rice bit vector.  The representation is that of Sec. 2.2
+ * "Representation": every bucket's node values in preorder, Golomb-Rice coded
+ * with a Rice parameter fixed per node size, the fixed-width parts of a
+ * bucket stored together and then its unary parts (Sec. 2.1 for both codes);
+ * the records of all buckets in one bit vector, located through the
+ * Elias-Fano coded prefix sums of bucket sizes and of record offsets (the
+ * paper's one combined sequence is stored here as two sequences).  Header:
+ * magic, version | rotation << 32, n, l | b << 32, nb.  Each Elias-Fano
+ * section: N, U, L, lower words, upper bits, upper words, then the lower
+ * bits and the upper bits.  Golomb-Rice section: bits, words, then the words.
+ * *bytes stays valid until rs_free(f).
  */
 int rs_serialize(const rs_mphf *f, const uint8_t **bytes, uint64_t *nbytes);
 
-/* Rebuild a queryable structure from serialised bytes (copied).
- * RS_ERR_CORRUPT when the header or the section sizes do not validate. */
+/* Rebuild a queryable structure from the bytes rs_serialize describes
+ * (Sec. 2.2 "Representation"; copied).  RS_ERR_CORRUPT when the header, the
+ * section sizes or the Elias-Fano sequences do not validate. */
 int rs_deserialize(const uint8_t *bytes, uint64_t nbytes, rs_mphf **out);
 
 /* Node values of one bucket in preorder, as chosen by the build (requires
@@ -280,10 +301,12 @@ int rs_get_stats(const rs_mphf *f, rs_stats *st);
  * Measurement helper for the integer roofline (not part of construction).
  * Issue rates of the VALU instruction classes a hash evaluation is made of,
  * in lane-operations per second on the current device, each measured over
- * independent dependency chains at full occupancy; and the rate of the hash
- * trial sequence itself (16 keys in registers, no memory), in hash
- * evaluations per second, over a few milliseconds and over about two seconds
- * (the clock held under sustained load).  No other side effects.
+ * independent dependency chains at full occupancy; and the rate of the
+ * evaluation sequence itself (hash, multiply-high reduction to a position,
+ * bit update: 19 VALU instructions, as in the search kernels; 16 keys in
+ * registers, no memory), in hash evaluations per second, over a few
+ * milliseconds and over about two seconds (the clock held under sustained
+ * load).  No other side effects.
  */
 typedef struct {
   double add_u32, xor_b32, mul_lo_u32, mul_hi_u32, mad_u64_u32, lshrrev_b64, lshl_add_u64,
@@ -305,6 +328,16 @@ int rs_calibrate_valu(rs_valu_rates *out);
  * (node_size).  -1 for arguments out of range.
  */
 double rs_attempt_work(uint32_t leaf_size, uint32_t node_size, uint32_t flags);
+
+/*
+ * Measurement and test helper (host only, no device needed): the rotation r
+ * that rotation fitting finds by table lookups (Sec. 4 "Lookup Tables") for
+ * the m-bit words a (hash positions of the keys of A) and b (of B): the
+ * smallest r with a | rot_m^r(b) = 2^m - 1, where rot_m^r moves bit p to
+ * (p + r) mod m, or m when no rotation fits.  The same tables and formula as
+ * the search kernels' lookup path.  0xFFFFFFFF for m outside 2..16.
+ */
+uint32_t rs_rotation_lookup(uint32_t m, uint32_t a, uint32_t b);
 
 void rs_free(rs_mphf *f);
 

@@ -27,6 +27,34 @@ constexpr uint32_t kHeaderWords = 5;
 constexpr uint32_t kEfHeaderWords = 6;
 constexpr size_t kAlign = 256;
 
+constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// The library's fixed device array, one copy per device, held until the
+// process ends.  It holds the starting seeds, the per-leaf-size tables (each
+// written once, by the first build or query of its leaf size on the device)
+// and, from kNoAllocAt on, the working memory and the encoded words of
+// rs_build_noalloc.  Host code never takes the array's name as an address:
+// device_get asks for its device address with hipGetSymbolAddress once per
+// device, with that device current, and every use goes through
+// Device::scratch.
+constexpr size_t kScratchBytes = 128ull << 20;
+constexpr size_t kSeedBytes = 4096;
+constexpr size_t kTableSlot = 3 * align_up(kTable * sizeof(uint32_t)) + align_up(kTable);
+constexpr size_t kNoAllocAt = kSeedBytes + (kMaxLeaf + 1) * kTableSlot;
+static __device__ __align__(256) uint64_t scratch[kScratchBytes / sizeof(uint64_t)];
+
+// Working memory of one job of RS_NOALLOC_MAX_KEYS keys at its most: host
+// keys staged (16 B) and two sorted copies (32 B) per key, one bucket per key
+// (24 B of sizes and lengths, 24 B of prefix sums and offsets), and per
+// stored node (never more than keys) 72 B of value, size, task, state and
+// flag; plus 1 MiB for the scan space, counters and worker table.  The
+// encoded words take what is left (at least 8 MiB: several hundred bits per
+// key, against the 1.5 to 2 bits per key that builds need).
+constexpr size_t kNoAllocWorkBound = (size_t)((1u << 19) + 2) * 168 + (1u << 20);
+static_assert(kSeedBytes >= kMaxDepth * sizeof(uint64_t), "seed space");
+static_assert(kNoAllocAt + kNoAllocWorkBound + (8u << 20) <= kScratchBytes,
+              "fixed array too small for 2^19 keys");
+
 int from_hip(hipError_t e) {
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return RS_ERR_OOM;
   return e == hipSuccess ? RS_OK : RS_ERR_DEVICE;
@@ -100,7 +128,7 @@ Context g_default[64];
 // (3x to 6x on a few thousand leaves of 22 or 24 keys); split_filter_tau = 16:
 // l = 16, b = 2000 8 % faster, while the shorter split searches of l <= 12
 // lose 1.5-2.6 % to it
-constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 19, 22, 16};
+constexpr rs_schedule kDefaultSchedule = {63, 4, 13, 12, 4, 16, 8, 8, 0, 0, 19, 22, 16, 0, 1};
 rs_schedule g_schedule = kDefaultSchedule;
 std::mutex g_schedule_mu;
 
@@ -128,12 +156,12 @@ int tables_for(Device& d, uint32_t l, Tables** out) {
     const std::vector<double>& sw = split_work_cached(l);
     std::vector<uint32_t> swfx(kTable);
     for (uint32_t m = 0; m < kTable; ++m) swfx[m] = (uint32_t)llround(ldexp(sw[m], kLeafWorkShift));
-    uint32_t *a = nullptr, *b = nullptr, *w = nullptr;
-    uint8_t* c = nullptr;
-    HIPCHECK(hipMalloc(&a, kTable * sizeof(uint32_t)));
-    HIPCHECK(hipMalloc(&b, kTable * sizeof(uint32_t)));
-    HIPCHECK(hipMalloc(&w, kTable * sizeof(uint32_t)));
-    HIPCHECK(hipMalloc(&c, kTable));
+    char* slot = d.scratch + kSeedBytes + (size_t)l * kTableSlot;
+    const size_t w32 = align_up(kTable * sizeof(uint32_t));
+    uint32_t* a = reinterpret_cast<uint32_t*>(slot);
+    uint32_t* b = reinterpret_cast<uint32_t*>(slot + w32);
+    uint32_t* w = reinterpret_cast<uint32_t*>(slot + 2 * w32);
+    uint8_t* c = reinterpret_cast<uint8_t*>(slot + 3 * w32);
     HIPCHECK(hipMemcpy(a, nc.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b, fb.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(w, swfx.data(), kTable * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -264,10 +292,17 @@ int device_get(Device** out) {
     if (hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, id) != hipSuccess ||
         d.wall_khz <= 0)
       d.wall_khz = 100000;
+    // this device's copy of the fixed array (the array's name is no device
+    // address in host code)
+    void* fixed = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&fixed, HIP_SYMBOL(scratch)));
+    if (!fixed) return RS_ERR_DEVICE;
+    d.scratch = static_cast<char*>(fixed);
     uint64_t h[kMaxDepth], st = 0;
     for (uint32_t i = 0; i < kMaxDepth; ++i) h[i] = splitmix_next(st);
-    HIPCHECK(hipMalloc(&d.start, sizeof h));
+    d.start = reinterpret_cast<uint64_t*>(d.scratch);
     HIPCHECK(hipMemcpy(d.start, h, sizeof h, hipMemcpyHostToDevice));
+    HIPCHECK(upload_rotation_tables());
     d.ready = true;
   }
   *out = &d;
@@ -410,112 +445,196 @@ struct Arrays {
   JobDev* jobs;
 };
 
-int encode_job(Context& c, const Arrays& A, JobPlan& jp, const JobInfo& info, double ms_sort,
-               double ms_search, uint32_t workers) {
-  const hipStream_t s = c.s;
-  const uint64_t nb = jp.nb;
-  const uint64_t* node_base = A.node_base + jp.off_base;
-  const uint64_t* vals = A.vals + jp.node_off;
-  const uint32_t* msz = A.msz + jp.node_off;
-  uint64_t* len = A.len + jp.bucket_base;
-  uint64_t* pos = A.pos + jp.off_base;
-  HIPCHECK(hipEventRecord(c.ev[4], s));
-  if (jp.total == 0) HIPCHECK(fill_u64(len, nb, 0, s));
-  else HIPCHECK(gr_lengths(node_base, nb, vals, msz, jp.T->tau, len, s));
-  HIPCHECK(scan_excl_u64(len, nb, pos, A.tmp, s));
-  uint64_t gr_bits = 0;
-  HIPCHECK(d2h(c, &gr_bits, pos + nb, sizeof gr_bits));
+hipError_t h2d_async(Context& c, void* dst, const void* src, size_t bytes) {
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.s);
+}
 
-  rs_mphf* f = new (std::nothrow) rs_mphf();
-  if (!f) return RS_ERR_OOM;
-  f->n = jp.n;
-  f->nb = nb;
-  f->l = jp.l;
-  f->b = jp.b;
-  f->rotation = (jp.flags & RS_FLAG_ROTATION) ? 1u : 0u;
-  f->device = c.dev->id;
-  f->efc = ef_layout(nb + 1, jp.n, kHeaderWords);
-  f->efp = ef_layout(nb + 1, gr_bits, f->efc.at + f->efc.words());
-  f->gr_at = f->efp.at + f->efp.words();
-  f->gr_bits = gr_bits;
-  f->gr_words = (gr_bits + 63) / 64;
-  const uint64_t nw = f->gr_at + 2 + f->gr_words;
-  auto fail = [&](int code) {
-    mphf_release(f);
-    return code;
-  };
-  if (ensure(c.out, nw * sizeof(uint64_t)) != hipSuccess) return fail(RS_ERR_OOM);
-  uint64_t* const dw = static_cast<uint64_t*>(c.out.p);
-  // header words, staged in the structure's host copy (alive until the copies end)
-  f->words.assign(nw, 0);
-  const uint64_t hdr[kHeaderWords] = {kMagic, kVersion | ((uint64_t)f->rotation << 32), jp.n,
-                                      (uint64_t)jp.l | ((uint64_t)jp.b << 32), nb};
-  memcpy(f->words.data(), hdr, sizeof hdr);
-  const EFLayout* efs[2] = {&f->efc, &f->efp};
-  for (int i = 0; i < 2; ++i) {
-    const EFLayout& e = *efs[i];
-    const uint64_t eh[6] = {e.N, e.U, e.L, e.lw, e.ub, e.uw};
-    memcpy(f->words.data() + e.at, eh, sizeof eh);
+// Encoding, first half, for every job that succeeded: the record length of
+// every bucket and their offsets; each job's record bits go to its
+// JobInfo::gr_bits, read back with the other per-job results.
+int encode_lengths(Context& c, const Arrays& A, const std::vector<JobPlan>& jobs) {
+  const hipStream_t s = c.s;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const JobPlan& jp = jobs[i];
+    if (jp.status) continue;
+    const uint64_t nb = jp.nb;
+    const uint64_t* node_base = A.node_base + jp.off_base;
+    uint64_t* len = A.len + jp.bucket_base;
+    uint64_t* pos = A.pos + jp.off_base;
+    if (jp.total == 0) HIPCHECK(fill_u64(len, nb, 0, s));
+    else HIPCHECK(gr_lengths(node_base, nb, A.vals + jp.node_off, A.msz + jp.node_off, jp.T->tau,
+                             len, s));
+    HIPCHECK(scan_excl_u64(len, nb, pos, A.tmp, s));
+    HIPCHECK(hipMemcpyAsync(&A.jinfo[i].gr_bits, pos + nb, sizeof(uint64_t),
+                            hipMemcpyDeviceToDevice, s));
   }
-  f->words[f->gr_at] = gr_bits;
-  f->words[f->gr_at + 1] = f->gr_words;
-  // zero the structure, place the headers; kernels write the rest
-  if (fill_u64(dw, nw, 0, s) != hipSuccess ||
-      hipMemcpyAsync(dw, f->words.data(), kHeaderWords * 8, hipMemcpyHostToDevice, s) !=
-          hipSuccess)
-    return fail(RS_ERR_DEVICE);
-  for (int i = 0; i < 2; ++i) {
-    const EFLayout& e = *efs[i];
-    if (hipMemcpyAsync(dw + e.at, f->words.data() + e.at, kEfHeaderWords * 8,
-                       hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(RS_ERR_DEVICE);
-  }
-  if (hipMemcpyAsync(dw + f->gr_at, f->words.data() + f->gr_at, 16, hipMemcpyHostToDevice, s) !=
-      hipSuccess)
-    return fail(RS_ERR_DEVICE);
-  uint64_t* gr = dw + f->gr_at + 2;
-  if (jp.total && gr_write(node_base, nb, vals, msz, jp.T->tau, pos, gr, s) != hipSuccess)
-    return fail(RS_ERR_DEVICE);
-  const uint64_t* xs[2] = {A.off + jp.off_base, pos};
-  for (int i = 0; i < 2; ++i) {
-    const EFLayout& e = *efs[i];
-    if (ef_write(xs[i], e.N, (uint32_t)e.L, dw + e.at + kEfHeaderWords,
-                 dw + e.at + kEfHeaderWords + e.lw, s) != hipSuccess)
-      return fail(RS_ERR_DEVICE);
-  }
-  if (hipEventRecord(c.ev[5], s) != hipSuccess) return fail(RS_ERR_DEVICE);
-  if (d2h(c, f->words.data(), dw, nw * 8) != hipSuccess) return fail(RS_ERR_DEVICE);
-  if (jp.flags & RS_FLAG_KEEP_VALUES) {
-    f->keep_vals.resize(jp.total);
-    f->keep_base.resize(nb + 1);
-    if ((jp.total && d2h(c, f->keep_vals.data(), vals, jp.total * 8) != hipSuccess) ||
-        d2h(c, f->keep_base.data(), node_base, (nb + 1) * 8) != hipSuccess)
-      return fail(RS_ERR_DEVICE);
-  }
-  rs_stats& st = f->stats;
-  memset(&st, 0, sizeof st);
-  st.n = jp.n;
-  st.nb = nb;
-  st.nodes = jp.total;
-  st.split_nodes = info.splits;
-  st.leaf_nodes = info.leaves;
-  st.useful_evals_split = info.evals_split;
-  st.useful_evals_leaf = info.evals_leaf;
-  st.early_exit_evals_leaf = ldexp((double)info.early_exit_leaf_fx, -(int)kLeafWorkShift);
-  st.early_exit_evals_split = ldexp((double)info.early_exit_split_fx, -(int)kLeafWorkShift);
-  st.gr_bits = gr_bits;
-  st.bytes = nw * 8;
-  st.max_bucket = jp.maxm;
-  st.workers = workers;
-  float ms = 0;
-  st.ms_sort = ms_sort;
-  st.ms_search = ms_search;
-  (void)hipEventElapsedTime(&ms, c.ev[4], c.ev[5]);
-  st.ms_encode = ms;
-  (void)hipEventElapsedTime(&ms, c.ev[0], c.ev[5]);
-  st.ms_total = ms;
-  jp.out = f;
   return RS_OK;
+}
+
+// Where one job's serialised words go: a new structure's host words, or
+// (rs_build_noalloc) the caller's buffer; the device words they are
+// assembled in.
+struct Out {
+  rs_mphf* f = nullptr;
+  uint64_t* hw = nullptr;
+  uint64_t* dw = nullptr;
+  uint64_t nw = 0;
+  EFLayout efc{}, efp{};
+  uint64_t gr_at = 0, gr_bits = 0, gr_words = 0;
+};
+
+// Encoding, second half: header words, Golomb-Rice records and both
+// Elias-Fano sequences of every job that succeeded, assembled on the device
+// and copied to the host, with one wait at the end.  Sets each job's status
+// and, on success, its structure.
+void encode_words(Context& c, const Arrays& A, std::vector<JobPlan>& jobs,
+                  const std::vector<JobInfo>& info, double ms_sort, double ms_search,
+                  uint32_t workers) {
+  const hipStream_t s = c.s;
+  const size_t nj = jobs.size();
+  std::vector<Out> outs(nj);
+  uint64_t own_words = 0;  // device words of the jobs that get a new structure
+  for (size_t i = 0; i < nj; ++i) {
+    JobPlan& jp = jobs[i];
+    if (jp.status) continue;
+    Out& o = outs[i];
+    o.gr_bits = info[i].gr_bits;
+    o.efc = ef_layout(jp.nb + 1, jp.n, kHeaderWords);
+    o.efp = ef_layout(jp.nb + 1, o.gr_bits, o.efc.at + o.efc.words());
+    o.gr_at = o.efp.at + o.efp.words();
+    o.gr_words = (o.gr_bits + 63) / 64;
+    o.nw = o.gr_at + 2 + o.gr_words;
+    if (jp.host_words) {
+      jp.nwords = o.nw;
+      if (o.nw > jp.host_cap) jp.status = RS_ERR_INVALID_ARG;
+      else if (o.nw > jp.dev_cap) jp.status = RS_ERR_OOM;
+      o.hw = jp.host_words;
+      o.dw = jp.dev_words;
+    } else {
+      own_words += o.nw;
+    }
+  }
+  auto fail_all = [&](int code) {
+    for (size_t i = 0; i < nj; ++i) {
+      if (jobs[i].status) continue;
+      mphf_release(outs[i].f);
+      outs[i].f = nullptr;
+      jobs[i].status = code;
+    }
+  };
+  if (own_words && ensure(c.out, own_words * sizeof(uint64_t)) != hipSuccess) {
+    fail_all(RS_ERR_OOM);
+    return;
+  }
+  uint64_t at = 0;
+  for (size_t i = 0; i < nj; ++i) {
+    JobPlan& jp = jobs[i];
+    if (jp.status || jp.host_words) continue;
+    Out& o = outs[i];
+    o.dw = static_cast<uint64_t*>(c.out.p) + at;
+    at += o.nw;
+    rs_mphf* f = new (std::nothrow) rs_mphf();
+    if (!f) {
+      fail_all(RS_ERR_OOM);
+      return;
+    }
+    f->n = jp.n;
+    f->nb = jp.nb;
+    f->l = jp.l;
+    f->b = jp.b;
+    f->rotation = (jp.flags & RS_FLAG_ROTATION) ? 1u : 0u;
+    f->device = c.dev->id;
+    f->efc = o.efc;
+    f->efp = o.efp;
+    f->gr_at = o.gr_at;
+    f->gr_bits = o.gr_bits;
+    f->gr_words = o.gr_words;
+    f->words.assign(o.nw, 0);
+    o.f = f;
+    o.hw = f->words.data();
+  }
+  bool ok = hipEventRecord(c.ev[4], s) == hipSuccess;
+  for (size_t i = 0; ok && i < nj; ++i) {
+    JobPlan& jp = jobs[i];
+    if (jp.status) continue;
+    const Out& o = outs[i];
+    const uint32_t rotation = (jp.flags & RS_FLAG_ROTATION) ? 1u : 0u;
+    // header words, staged in the host words (alive until the copies end)
+    const uint64_t hdr[kHeaderWords] = {kMagic, kVersion | ((uint64_t)rotation << 32), jp.n,
+                                        (uint64_t)jp.l | ((uint64_t)jp.b << 32), jp.nb};
+    memcpy(o.hw, hdr, sizeof hdr);
+    const EFLayout* efs[2] = {&o.efc, &o.efp};
+    for (int k = 0; k < 2; ++k) {
+      const EFLayout& e = *efs[k];
+      const uint64_t eh[6] = {e.N, e.U, e.L, e.lw, e.ub, e.uw};
+      memcpy(o.hw + e.at, eh, sizeof eh);
+    }
+    o.hw[o.gr_at] = o.gr_bits;
+    o.hw[o.gr_at + 1] = o.gr_words;
+    // zero the structure, place the headers; kernels write the rest
+    ok = fill_u64(o.dw, o.nw, 0, s) == hipSuccess &&
+         h2d_async(c, o.dw, o.hw, kHeaderWords * 8) == hipSuccess;
+    for (int k = 0; ok && k < 2; ++k)
+      ok = h2d_async(c, o.dw + efs[k]->at, o.hw + efs[k]->at, kEfHeaderWords * 8) == hipSuccess;
+    ok = ok && h2d_async(c, o.dw + o.gr_at, o.hw + o.gr_at, 16) == hipSuccess;
+    if (ok && jp.total)
+      ok = gr_write(A.node_base + jp.off_base, jp.nb, A.vals + jp.node_off, A.msz + jp.node_off,
+                    jp.T->tau, A.pos + jp.off_base, o.dw + o.gr_at + 2, s) == hipSuccess;
+    const uint64_t* xs[2] = {A.off + jp.off_base, A.pos + jp.off_base};
+    for (int k = 0; ok && k < 2; ++k) {
+      const EFLayout& e = *efs[k];
+      ok = ef_write(xs[k], e.N, (uint32_t)e.L, o.dw + e.at + kEfHeaderWords,
+                    o.dw + e.at + kEfHeaderWords + e.lw, s) == hipSuccess;
+    }
+  }
+  ok = ok && hipEventRecord(c.ev[5], s) == hipSuccess;
+  for (size_t i = 0; ok && i < nj; ++i) {
+    JobPlan& jp = jobs[i];
+    if (jp.status) continue;
+    Out& o = outs[i];
+    ok = hipMemcpyAsync(o.hw, o.dw, o.nw * 8, hipMemcpyDeviceToHost, s) == hipSuccess;
+    if (ok && (jp.flags & RS_FLAG_KEEP_VALUES)) {
+      o.f->keep_vals.resize(jp.total);
+      o.f->keep_base.resize(jp.nb + 1);
+      ok = (!jp.total || hipMemcpyAsync(o.f->keep_vals.data(), A.vals + jp.node_off, jp.total * 8,
+                                        hipMemcpyDeviceToHost, s) == hipSuccess) &&
+           hipMemcpyAsync(o.f->keep_base.data(), A.node_base + jp.off_base, (jp.nb + 1) * 8,
+                          hipMemcpyDeviceToHost, s) == hipSuccess;
+    }
+  }
+  ok = ok && hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    fail_all(RS_ERR_DEVICE);
+    return;
+  }
+  float ms_enc = 0, ms_all = 0;
+  (void)hipEventElapsedTime(&ms_enc, c.ev[4], c.ev[5]);
+  (void)hipEventElapsedTime(&ms_all, c.ev[0], c.ev[5]);
+  for (size_t i = 0; i < nj; ++i) {
+    JobPlan& jp = jobs[i];
+    if (jp.status || !outs[i].f) continue;
+    const JobInfo& in = info[i];
+    rs_stats& st = outs[i].f->stats;
+    memset(&st, 0, sizeof st);
+    st.n = jp.n;
+    st.nb = jp.nb;
+    st.nodes = jp.total;
+    st.split_nodes = in.splits;
+    st.leaf_nodes = in.leaves;
+    st.useful_evals_split = in.evals_split;
+    st.useful_evals_leaf = in.evals_leaf;
+    st.early_exit_evals_leaf = ldexp((double)in.early_exit_leaf_fx, -(int)kLeafWorkShift);
+    st.early_exit_evals_split = ldexp((double)in.early_exit_split_fx, -(int)kLeafWorkShift);
+    st.gr_bits = outs[i].gr_bits;
+    st.bytes = outs[i].nw * 8;
+    st.max_bucket = jp.maxm;
+    st.workers = workers;
+    st.ms_sort = ms_sort;
+    st.ms_search = ms_search;
+    st.ms_encode = ms_enc;
+    st.ms_total = ms_all;
+    jp.out = outs[i].f;
+  }
 }
 
 }  // namespace
@@ -613,6 +732,8 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
                              &A.jinfo[i].error, s));
     HIPCHECK(node_counts(A.cnt + j.bucket_base, j.nb, j.T->nodecnt, A.nodes + j.bucket_base, s));
     HIPCHECK(scan_excl_u64(A.nodes + j.bucket_base, j.nb, A.node_base + j.off_base, A.tmp, s));
+    HIPCHECK(hipMemcpyAsync(&A.jinfo[i].nodes, A.node_base + j.off_base + j.nb, sizeof(uint64_t),
+                            hipMemcpyDeviceToDevice, s));
   }
   HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
   uint64_t total = 0;
@@ -624,7 +745,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
       j.status = -(int)hinfo[i].error;
       continue;
     }
-    HIPCHECK(d2h(c, &j.total, A.node_base + j.off_base + j.nb, sizeof(uint64_t)));
+    j.total = hinfo[i].nodes;
     j.node_off = total;
     total += j.total;
     maxm = j.maxm > maxm ? j.maxm : maxm;
@@ -659,20 +780,24 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
       if (words < need) words = need;
     }
   }
-  const uint32_t mode = bucket_mode ? kSearchBucket : filter ? kSearchFilter : kSearchNode;
+  const uint32_t mode = bucket_mode ? (sched.bucket_wave ? kSearchBucketWave : kSearchBucket)
+                       : filter    ? kSearchFilter
+                                   : kSearchNode;
 
   // 2. seed search over all nodes of all jobs, one persistent launch
+  std::vector<JobDev> jd(nj);  // read by a copy that ends before the wait after the search
   if (total) {
     const uint32_t lds = bucket_mode ? bucket_lds_bytes(maxm) : words * (uint32_t)sizeof(uint64_t);
     int per_cu = 0;
     HIPCHECK(search_occupancy(lds, &per_cu, mode));
     if (per_cu < 1) per_cu = 1;
     const uint32_t occ = (uint32_t)per_cu * (uint32_t)d.cus;
+    // one-wave workers: four per four-wave worker the caps allow
+    if (mode == kSearchBucketWave) workers *= 4;
     if (workers > occ) workers = occ;
     HIPCHECK(init_states(A.states, total, s));
     HIPCHECK(fill_u32(A.ready, total, 0, s));
-    HIPCHECK(fill_u32(A.active_u32, workers, 0xFFFFFFFFu, s));
-    std::vector<JobDev> jd(nj);
+    HIPCHECK(fill_u32(A.active_u32, workers < wmax ? workers : wmax, 0xFFFFFFFFu, s));
     for (uint32_t i = 0; i < nj; ++i) {
       JobPlan& j = jobs[i];
       JobDev& g = jd[i];
@@ -691,8 +816,9 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
       g.ua = sh.ua;
       g.rotation = (j.flags & RS_FLAG_ROTATION) ? 1u : 0u;
     }
-    HIPCHECK(h2d(c, A.jobs, jd.data(), nj * sizeof(JobDev)));
-    HIPCHECK(h2d(c, &A.ctl->total, &total, sizeof(uint64_t)));
+    // (jd and total stay alive until the wait after the search)
+    HIPCHECK(h2d_async(c, A.jobs, jd.data(), nj * sizeof(JobDev)));
+    HIPCHECK(h2d_async(c, &A.ctl->total, &total, sizeof(uint64_t)));
     for (uint32_t i = 0; i < nj; ++i) {
       JobPlan& j = jobs[i];
       if (j.status || !j.total) continue;
@@ -722,6 +848,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     // the leaves are too few to keep every worker busy to the end
     P.join_leaf_tau = small ? sched.join_leaf_tau : 0u;
     P.split_filter_tau = filter ? sched.split_filter_tau : 0u;
+    P.rotation_lookup = sched.rotation_lookup;
     // s_memrealtime ticks (wall_khz per millisecond)
     P.stall_ticks = sched.stall_guard_us ? (uint64_t)d.wall_khz * sched.stall_guard_us / 1000ull
                                          : (uint64_t)d.wall_khz * 1000ull * 10ull;
@@ -732,8 +859,18 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     HIPCHECK(hipEventRecord(c.ev[3], s));
   }
   HIPCHECK(hipEventRecord(c.ev[4], s));
+  // useful work of every job, counted from its node values (harmless after a
+  // stopped search, whose results are dropped), read back with the control
+  // block in one wait
+  for (uint32_t i = 0; i < nj; ++i) {
+    const JobPlan& j = jobs[i];
+    if (j.status || !j.total) continue;
+    HIPCHECK(work_counts(A.vals + j.node_off, A.msz + j.node_off, j.total, j.l,
+                         (j.flags & RS_FLAG_ROTATION) ? 1u : 0u, j.T->split_work, A.jinfo + i, s));
+  }
   Control h_ctl;
-  HIPCHECK(d2h(c, &h_ctl, A.ctl, sizeof h_ctl));
+  HIPCHECK(hipMemcpyAsync(&h_ctl, A.ctl, sizeof h_ctl, hipMemcpyDeviceToHost, s));
+  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
   if (h_ctl.error && getenv("RS_DEBUG")) {
     fprintf(stderr,
             "[rs debug] error %u: node %llu slot %llu m %u depth %u key_off %llu np %016llx "
@@ -748,29 +885,21 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   int search_rc = RS_OK;
   if (h_ctl.error) search_rc = -(int)h_ctl.error;
   else if (h_ctl.finished != total) search_rc = RS_ERR_DEVICE;
-  if (!search_rc)
-    for (uint32_t i = 0; i < nj; ++i) {
-      const JobPlan& j = jobs[i];
-      if (j.status || !j.total) continue;
-      HIPCHECK(work_counts(A.vals + j.node_off, A.msz + j.node_off, j.total, j.l,
-                           (j.flags & RS_FLAG_ROTATION) ? 1u : 0u, j.T->split_work,
-                           A.jinfo + i, s));
-    }
-  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
   float ms_sort = 0, ms_search = 0;
   (void)hipEventElapsedTime(&ms_sort, c.ev[1], c.ev[2]);
   (void)hipEventElapsedTime(&ms_search, c.ev[3], c.ev[4]);
-
-  // 3. encode every job that succeeded
-  for (uint32_t i = 0; i < nj; ++i) {
-    JobPlan& j = jobs[i];
-    if (j.status) continue;
-    if (search_rc) {
-      j.status = search_rc;
-      continue;
-    }
-    j.status = encode_job(c, A, j, hinfo[i], ms_sort, ms_search, workers);
+  if (search_rc) {
+    for (JobPlan& j : jobs)
+      if (!j.status) j.status = search_rc;
+    return RS_OK;
   }
+
+  // 3. encode every job that succeeded: record lengths (one wait for all
+  // jobs' record bits), then the words (one wait)
+  const int enc_rc = encode_lengths(c, A, jobs);
+  if (enc_rc) return enc_rc;
+  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
+  encode_words(c, A, jobs, hinfo, ms_sort, ms_search, workers);
   return RS_OK;
 }
 
@@ -1030,6 +1159,24 @@ double rs_attempt_work(uint32_t leaf_size, uint32_t node_size, uint32_t flags) {
     return ldexp((double)t.fx[node_size], -(int)kLeafWorkShift);
   }
   return split_work_cached(leaf_size)[node_size];
+}
+
+uint32_t rs_rotation_lookup(uint32_t m, uint32_t a, uint32_t b) {
+  if (m < 2 || m > kRotLookupMaxM) return 0xFFFFFFFFu;
+  static std::vector<uint16_t> table;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    table.resize(kRotLookupEntries);
+    rotation_tables(table.data());
+  });
+  const uint32_t full = (1u << m) - 1u;
+  a &= full;
+  b &= full;
+  const uint32_t ea = table[(1u << m) + a], eb = table[(1u << m) + (~b & full)];
+  uint32_t r = ((eb & 0xFFu) + m - (ea & 0xFFu)) % m;
+  r %= ea >> 8;
+  const uint32_t rb = r ? ((b << r) | (b >> (m - r))) & full : b;
+  return (a | rb) == full ? r : m;
 }
 
 int rs_get_schedule(rs_schedule* sc) {

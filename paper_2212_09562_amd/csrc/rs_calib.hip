@@ -51,31 +51,37 @@ __global__ void __launch_bounds__(kCalThreads) k_calib(uint32_t* out, uint32_t i
   out[t] = (uint32_t)r ^ (uint32_t)(r >> 32);
 }
 
-// The hash sequence of a bijection trial: 16 keys in registers, lane = seed.
-__global__ void __launch_bounds__(kCalThreads) k_calib_hash(uint32_t* out, uint32_t iters, uint32_t seed) {
+// The evaluation sequence of a bijection trial: 16 keys in registers, lane =
+// seed, the leaf size a kernel argument (as in the search kernels, so the
+// reduction stays a multiply-high and the last xorshift is kept: 19 VALU
+// instructions per evaluation, the sequence the roofline counts).
+__global__ void __launch_bounds__(kCalThreads) k_calib_hash(uint32_t* out, uint32_t iters,
+                                                            uint32_t seed, uint32_t M) {
   const uint32_t t = blockIdx.x * kCalThreads + threadIdx.x;
   uint64_t keys[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) keys[j] = mix64(seed + j);
   uint64_t X = seed + t;
+  const uint32_t full = (1u << M) - 1u;
   uint32_t acc = 0;
   for (uint32_t i = 0; i < iters; ++i) {
     uint32_t mask = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) mask |= 1u << reduce(hash_top(keys[j], X), 16u);
-    acc += mask == 0xFFFFu;
+    for (int j = 0; j < 16; ++j) mask |= 1u << reduce(hash_top(keys[j], X), M);
+    acc += mask == full;
     X += 1ull << 20;
   }
   out[t] = acc;
 }
 
-template <typename K>
-double time_kernel(K kernel, uint32_t blocks, uint32_t iters, uint32_t* buf) {
+template <typename K, typename... A>
+double time_kernel(K kernel, uint32_t blocks, uint32_t iters, uint32_t* buf, A... extra) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kCalThreads), 0, 0, buf, iters / 8, 12345u);
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kCalThreads), 0, 0, buf, iters / 8, 12345u,
+                     extra...);
   (void)hipEventRecord(e0, 0);
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kCalThreads), 0, 0, buf, iters, 12345u);
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kCalThreads), 0, 0, buf, iters, 12345u, extra...);
   (void)hipEventRecord(e1, 0);
   (void)hipEventSynchronize(e1);
   float ms = 0;
@@ -99,7 +105,8 @@ extern "C" int rs_calibrate_valu(rs_valu_rates* out) {
   const uint32_t blocks = (uint32_t)cus * 8;  // 8 waves per SIMD
   uint32_t* buf = nullptr;
   if (hipMalloc(&buf, (size_t)blocks * kCalThreads * sizeof(uint32_t)) != hipSuccess) return RS_ERR_OOM;
-  const uint32_t iters = 4096;
+  // long enough (several milliseconds) that launch and drain are a small part
+  const uint32_t iters = 1u << 16;
   const double lanes = (double)blocks * kCalThreads;
   const double per = lanes * iters * 8.0;
   double s[8];
@@ -112,13 +119,13 @@ extern "C" int rs_calibrate_valu(rs_valu_rates* out) {
   s[6] = time_kernel(k_calib<6>, blocks, iters, buf);
   s[7] = time_kernel(k_calib<7>, blocks, iters, buf);
   const uint32_t hiters = 2048;
-  const double sh = time_kernel(k_calib_hash, blocks, hiters, buf);
+  const double sh = time_kernel(k_calib_hash, blocks, hiters, buf, 16u);
   // the same loop for about two seconds: the clock the chip holds under a
   // sustained full-occupancy integer load
   const double per_iter = sh / hiters;
   uint32_t long_iters = per_iter > 0 ? (uint32_t)(2.0 / per_iter) : 0;
   if (long_iters < hiters) long_iters = hiters;
-  const double sl = time_kernel(k_calib_hash, blocks, long_iters, buf);
+  const double sl = time_kernel(k_calib_hash, blocks, long_iters, buf, 16u);
   (void)hipFree(buf);
   for (double v : s)
     if (v <= 0) return RS_ERR_DEVICE;

@@ -20,17 +20,7 @@ struct Tables {
   uint32_t* split_work = nullptr;  // split_work_table in units of 2^-kLeafWorkShift
 };
 
-// Read-only after initialisation; shared by every context on the device.
-struct Device {
-  bool ready = false;
-  int id = 0;
-  int cus = 0;
-  int wall_khz = 100000;
-  int lds_per_block = 65536;
-  uint64_t* start = nullptr;  // starting seed of depth d: SplitMix64(0) output d+1
-  Tables tables[kMaxLeaf + 1];
-  std::mutex mu;  // guards lazy initialisation of the tables
-};
+struct Device;
 
 struct Buffer {
   void* p = nullptr;
@@ -51,6 +41,23 @@ struct Context {
   std::mutex mu;
 };
 
+// Read-only after initialisation; shared by every context on the device.
+// The starting seeds and the tables live in the library's fixed device array
+// (`scratch` in rs_api.hip), found at initialisation; so does the working
+// memory of rs_build_noalloc, which builds through `noalloc` (its lock
+// serialises those calls).
+struct Device {
+  bool ready = false;
+  int id = 0;
+  int cus = 0;
+  int wall_khz = 100000;
+  int lds_per_block = 65536;
+  char* scratch = nullptr;    // device address of the fixed array on this device
+  uint64_t* start = nullptr;  // starting seed of depth d: SplitMix64(0) output d+1
+  Tables tables[kMaxLeaf + 1];
+  std::mutex mu;  // guards lazy initialisation of the tables
+};
+
 int device_get(Device** out);
 int context_init(Context& c, Device* d);
 void context_destroy(Context& c);
@@ -67,6 +74,13 @@ struct JobPlan {
   int status = RS_OK;
   Tables* T = nullptr;
   rs_mphf* out = nullptr;
+  // rs_build_noalloc: the serialised words go to host_words (host_cap words)
+  // through dev_words (dev_cap words of the fixed array) instead of a new
+  // structure; nwords receives their count
+  uint64_t* host_words = nullptr;
+  uint64_t host_cap = 0, nwords = 0;
+  uint64_t* dev_words = nullptr;
+  uint64_t dev_cap = 0;
 };
 
 // Upper bound of the device working memory of a build of these jobs

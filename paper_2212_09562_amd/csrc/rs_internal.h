@@ -140,6 +140,8 @@ struct JobInfo {
   uint64_t evals_split, evals_leaf, splits, leaves;
   uint64_t early_exit_leaf_fx;   // see LeafWork; in units of 2^-kLeafWorkShift evaluations
   uint64_t early_exit_split_fx;  // the same for splits (split_work_table)
+  uint64_t nodes;    // stored nodes of the job (copied from its node-count scan)
+  uint64_t gr_bits;  // bits of its Golomb-Rice records (copied from their scan)
 };
 
 // Expected hash evaluations of one failed leaf attempt of size m when the
@@ -183,6 +185,13 @@ struct Control {
 };
 static_assert(sizeof(Control) % 256 == 0, "Control lines");
 
+// Rotation fitting with lookup tables (Sec. 4): for every leaf size m up to
+// kRotLookupMaxM and every m-bit word x, entry (1 << m) + x holds in bits
+// 0..7 the rotation t with rot_m^t(x) smallest (the first such t) and in
+// bits 8..15 the period of x under rotation (m when x has no shorter one).
+constexpr uint32_t kRotLookupMaxM = 16;
+constexpr uint32_t kRotLookupEntries = 2u << kRotLookupMaxM;
+
 // Whole-bucket mode: dynamic LDS of a worker = a stack of pending nodes, then
 // per key its hashed word, a scratch word, its A/B class and a scratch class.
 constexpr uint32_t kBucketStackBytes = 64 * 24;
@@ -192,8 +201,8 @@ __host__ __device__ inline uint32_t bucket_lds_bytes(uint32_t cap) {
 }
 
 // Search kernels: nodes as tasks; the same with filtered leaves; whole
-// buckets per worker.
-enum : uint32_t { kSearchNode = 0, kSearchFilter = 1, kSearchBucket = 2 };
+// buckets per worker of four waves; whole buckets per wave.
+enum : uint32_t { kSearchNode = 0, kSearchFilter = 1, kSearchBucket = 2, kSearchBucketWave = 3 };
 
 struct SearchParams {
   const JobDev* jobs;
@@ -214,6 +223,8 @@ struct SearchParams {
   uint32_t join_leaf_tau;    // leaves with tau at least this are searched in claimed chunks (0: none)
   uint32_t split_filter_tau;  // lower/upper splits with tau at least this drop attempts at an
                               // overfull child (0: never)
+  uint32_t rotation_lookup;   // rotation leaves of at most kRotLookupMaxM keys find their
+                              // rotation by two table lookups (0: the wave tries them all)
   uint64_t stall_ticks;  // bug guard on idle time (s_memrealtime ticks)
 };
 

@@ -41,6 +41,11 @@ LeafWork leaf_work_table(bool rotation);
 // kTable, for leaf size l (0 for leaf sizes; host).
 std::vector<double> split_work_table(uint32_t l);
 
+// The rotation lookup tables (kRotLookupEntries entries, host) and their
+// upload to the current device's copy of the search kernels' table.
+void rotation_tables(uint16_t* out);
+hipError_t upload_rotation_tables();
+
 // Seed search (persistent kernel).
 hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, uint32_t mode = kSearchNode);
 hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);

@@ -208,6 +208,7 @@ __global__ void __launch_bounds__(256) k_work_counts(const uint64_t* vals, const
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t m = msz[i];
     const uint64_t v = vals[i];
+    if (m < 2) continue;  // no stored node has fewer than two keys (a stopped search leaves stale sizes)
     if (m > l) {
       es += (v + 1) * m;
       se += v * split_fx[m < kTable ? m : kTable - 1] + ((uint64_t)m << kLeafWorkShift);

@@ -86,6 +86,27 @@ __device__ __forceinline__ uint32_t rot_m(uint32_t x, uint32_t r, uint32_t m, ui
   return ((x << r) | (x >> (m - r))) & full;
 }
 
+// The rotation lookup tables (layout in rs_internal.h), written once per
+// device by upload_rotation_tables.
+__device__ uint16_t g_rot_lookup[kRotLookupEntries];
+
+// Rotation fitting by table lookups (Sec. 4 "Lookup Tables"): b fills the
+// holes of a after rotating by r exactly when the complement of b, rotated by
+// r, equals a, so both are in one rotation orbit and r = t[~b] - t[a] modulo
+// m works; when a repeats with period p the valid rotations are r + k p and
+// the smallest is r mod p.  Returns that smallest valid r, or m when no
+// rotation fits.
+__device__ __forceinline__ uint32_t rot_lookup(uint32_t a, uint32_t b, uint32_t m, uint32_t full) {
+  const uint16_t* t = g_rot_lookup + (1u << m);
+  const uint32_t ea = t[a];
+  const uint32_t eb = t[~b & full];
+  uint32_t r = (eb & 0xFFu) + m - (ea & 0xFFu);
+  if (r >= m) r -= m;
+  const uint32_t p = ea >> 8;
+  while (r >= p) r -= p;
+  return (a | rot_m(b, r, m, full)) == full ? r : m;
+}
+
 // Everything a worker needs to know about its current task, wave-uniform.
 struct Node {
   uint32_t kind, m, k, unit, last;
@@ -96,14 +117,14 @@ struct Node {
   uint32_t full;    // 1 when every child has exactly unit keys
   uint32_t na;      // leaf keys of class A (staged first)
   uint32_t mult;    // value per attempt: m for rotation leaves, else 1
-  uint32_t rotation;
+  uint32_t rotation;  // leaves: 0 brute force, 1 rotation fitting, 2 the same by table lookups
   uint32_t fullmask;
   uint64_t start;
   uint64_t cap;  // attempts after which the search is reported as failed
 };
 
 __device__ Node make_node(const Task& t, const JobDev& J, const uint64_t* start,
-                          uint32_t cap_shift) {
+                          uint32_t cap_shift, uint32_t lookup) {
   Node c;
   Shape s;
   s.l = uni(J.l);
@@ -127,6 +148,7 @@ __device__ Node make_node(const Task& t, const JobDev& J, const uint64_t* start,
   if (c.kind == kBinary) c.thr = (uint32_t)((((uint64_t)c.unit << 32) + c.m - 1) / c.m);
   c.magic = c.unit ? ((1u << 20) + c.unit - 1) / c.unit : 0;
   c.mult = (c.kind == kLeaf && c.rotation) ? c.m : 1u;
+  if (lookup && c.kind == kLeaf && c.rotation && c.m <= kRotLookupMaxM) c.rotation = 2;
   c.fullmask = c.m >= 32 ? ~0u : ((1u << c.m) - 1u);
   c.na = 0;
   // tau is within 2 bits of log2 of the expected number of trials, so a
@@ -159,6 +181,7 @@ __device__ __forceinline__ uint64_t round_leaf_brute(const uint64_t* keys, const
 // some rotation of b must fill the holes of a.  Lanes passing the popcount
 // test are checked in lane order, each by the whole wave: lane r tests
 // rotation r, so the lowest valid r comes from one ballot.
+template <bool kLookup>
 __device__ __forceinline__ uint64_t round_leaf_rot(const uint64_t* keys, const Node& c,
                                                     uint64_t a0) {
   const uint32_t lane = lane_id();
@@ -169,6 +192,14 @@ __device__ __forceinline__ uint64_t round_leaf_rot(const uint64_t* keys, const N
 #pragma unroll 4
   for (uint32_t i = c.na; i < c.m; ++i) b |= 1u << reduce(hash_top(keys[i], X), c.m);
   bool cand = (uint32_t)__popc(a) == c.na && (uint32_t)__popc(b) == c.m - c.na;
+  if (kLookup && c.rotation == 2) {
+    // every candidate finds its rotation itself
+    const uint32_t r = cand ? rot_lookup(a, b, c.m, c.fullmask) : c.m;
+    const uint64_t okm = __ballot(r < c.m);
+    if (!okm) return kInf;
+    const uint32_t L = (uint32_t)__builtin_ctzll(okm);
+    return (a0 + L) * c.m + __builtin_amdgcn_readlane(r, L);
+  }
   uint64_t cm = __ballot(cand);
   while (cm) {
     const uint32_t L = (uint32_t)__builtin_ctzll(cm);
@@ -266,11 +297,15 @@ __device__ __forceinline__ void run_chunk(const uint64_t* keys, const Node& c, u
   }
 }
 
+// kLookup: the rotation lookup path is compiled in (not in the filter kernel,
+// whose register budget it would break; its long leaves rarely reach the
+// rotation test).
+template <bool kLookup>
 __device__ void eval_chunk(const uint64_t* keys, const Node& c, uint64_t first, uint32_t rounds,
                            uint64_t* s_best) {
   switch (c.kind) {
     case kLeaf:
-      if (c.rotation) run_chunk(keys, c, first, rounds, s_best, round_leaf_rot);
+      if (c.rotation) run_chunk(keys, c, first, rounds, s_best, round_leaf_rot<kLookup>);
       else run_chunk(keys, c, first, rounds, s_best, round_leaf_brute);
       break;
     case kLower:
@@ -366,7 +401,8 @@ __device__ void run_leaf_filtered(const Node& c, uint64_t first, uint32_t rounds
     const uint64_t att = attempt_of(e >> 24);
     const uint32_t w1 = (uint32_t)e & 0xFFFFFFu;
     const uint32_t w2 = leaf_bits(keys, lo2, hi2, c.start + att * c.mult, c.m);
-    uint64_t cm = __ballot(v && (uint32_t)__popc(w2) == hi2 - lo2);
+    const bool cand = v && (uint32_t)__popc(w2) == hi2 - lo2;
+    uint64_t cm = __ballot(cand);
     if (!c.rotation) return cm ? readlane64(att, (uint32_t)__builtin_ctzll(cm)) : kInf;
     while (cm) {
       const uint32_t L = (uint32_t)__builtin_ctzll(cm);
@@ -738,7 +774,7 @@ template <bool kFilter>
 __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
                          const JobDev& J, uint64_t slot) {
   const uint32_t tid = threadIdx.x;
-  Node c = make_node(t, J, P.start, P.cap_shift);
+  Node c = make_node(t, J, P.start, P.cap_shift, kFilter ? 0u : P.rotation_lookup);
   stage_keys(t, J, c, s_keys, &sh.na);
   if (tid == 0) sh.best = kInf;
   __syncthreads();
@@ -751,7 +787,7 @@ __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, co
   if (kFilter && filtered_leaf(P, tau))
     run_leaf_filtered(c, 0, rounds, patience(c, tau), &sh.best);
   else
-    eval_chunk(s_keys, c, 0, rounds, &sh.best);
+    eval_chunk<!kFilter>(s_keys, c, 0, rounds, &sh.best);
   __syncthreads();
   const uint64_t v = sh.best;
   if (v == kInf) {
@@ -775,6 +811,42 @@ struct Frame {
 };
 constexpr uint32_t kFrames = kBucketStackBytes / sizeof(Frame);
 static_assert(kFrames * sizeof(Frame) == kBucketStackBytes, "stack layout");
+
+// Stable partition of a split node's keys (with their A/B classes) by child
+// under value v, in LDS through a scratch copy, then back.  One wave.
+__device__ void partition_lds(const SearchParams& P, const Node& c, uint64_t v, uint64_t* keys,
+                              uint8_t* cls, uint64_t* tmp, uint8_t* ctmp) {
+  const uint32_t lane = lane_id();
+  const uint64_t X = c.start + v;
+  uint32_t run = 0;  // lane j: keys already placed in child j
+  for (uint32_t g = 0; g < c.m; g += 64) {
+    const uint32_t i = g + lane;
+    const bool ok = i < c.m;
+    const uint64_t w = ok ? keys[i] : 0;
+    const uint8_t b = ok ? cls[i] : 0;
+    const uint32_t p = reduce(hash_top(w, X), c.m);
+    uint32_t ch = c.kind == kBinary ? (p >= c.unit ? 1u : 0u) : p / c.unit;
+    if (!ok) ch = 0xFFFFFFFFu;
+    const uint32_t at0 = (uint32_t)__shfl((int)run, ok ? (int)ch : 0);
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < c.k; ++j) {
+      const uint64_t mk = __ballot(ch == j);
+      if (ch == j) rank = (uint32_t)__popcll(mk & mask_below(lane));
+      if (lane == j) run += (uint32_t)__popcll(mk);
+    }
+    const uint32_t at = ch * c.unit + at0 + rank;
+    if (ok && at < c.m) {
+      tmp[at] = w;
+      ctmp[at] = b;
+    }
+  }
+  const bool good = lane >= c.k || run == (lane + 1 < c.k ? c.unit : c.last);
+  if (__ballot(!good) != 0 && lane == 0) set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
+  for (uint32_t i = lane; i < c.m; i += 64) {
+    keys[i] = tmp[i];
+    cls[i] = ctmp[i];
+  }
+}
 
 __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, const Task& t,
                            const JobDev& J) {
@@ -827,7 +899,7 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
     nt.job = t.job;
     uint64_t* keys = s_keys + nt.key_off;
     uint8_t* cls = s_cls + nt.key_off;
-    Node c = make_node(nt, J, P.start, P.cap_shift);
+    Node c = make_node(nt, J, P.start, P.cap_shift, P.rotation_lookup);
     if (c.kind == kLeaf && tid < 64) {
       // the keys of A (class bit clear) first, in a stable order
       const bool v = lane < c.m;
@@ -843,7 +915,7 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
     __syncthreads();
     if (c.kind == kLeaf) c.na = uni(sh.na);
     const uint64_t max_rounds = c.cap / kWG + 1;
-    eval_chunk(keys, c, 0, max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu,
+    eval_chunk<true>(keys, c, 0, max_rounds < 0xFFFFFFFFull ? (uint32_t)max_rounds : 0xFFFFFFFFu,
                &sh.best);
     __syncthreads();
     const uint64_t v = sh.best;
@@ -852,39 +924,8 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
         record_failure(P.ctl, nt, kNoSlot, P.states, 0);
       continue;  // the error ends the loop at the next pop
     }
-    if (c.kind != kLeaf && tid < 64) {
-      // stable partition of the node's keys (with their classes) by child,
-      // through the scratch copy, then back
-      const uint64_t X = c.start + v;
-      uint32_t run = 0;  // lane j: keys already placed in child j
-      for (uint32_t g = 0; g < c.m; g += 64) {
-        const uint32_t i = g + lane;
-        const bool ok = i < c.m;
-        const uint64_t w = ok ? keys[i] : 0;
-        const uint8_t b = ok ? cls[i] : 0;
-        const uint32_t p = reduce(hash_top(w, X), c.m);
-        uint32_t ch = c.kind == kBinary ? (p >= c.unit ? 1u : 0u) : p / c.unit;
-        if (!ok) ch = 0xFFFFFFFFu;
-        const uint32_t at0 = (uint32_t)__shfl((int)run, ok ? (int)ch : 0);
-        uint32_t rank = 0;
-        for (uint32_t j = 0; j < c.k; ++j) {
-          const uint64_t mk = __ballot(ch == j);
-          if (ch == j) rank = (uint32_t)__popcll(mk & mask_below(lane));
-          if (lane == j) run += (uint32_t)__popcll(mk);
-        }
-        const uint32_t at = ch * c.unit + at0 + rank;
-        if (ok && at < c.m) {
-          s_tmp[nt.key_off + at] = w;
-          s_ctmp[nt.key_off + at] = b;
-        }
-      }
-      const bool good = lane >= c.k || run == (lane + 1 < c.k ? c.unit : c.last);
-      if (__ballot(!good) != 0 && lane == 0) set_error(P.ctl, (uint32_t)(-RS_ERR_DEVICE));
-      for (uint32_t i = lane; i < c.m; i += 64) {
-        keys[i] = s_tmp[nt.key_off + i];
-        cls[i] = s_ctmp[nt.key_off + i];
-      }
-    }
+    if (c.kind != kLeaf && tid < 64)
+      partition_lds(P, c, v, keys, cls, s_tmp + nt.key_off, s_ctmp + nt.key_off);
     if (tid == 0) {
       J.vals[nt.node] = v;
       J.msz[nt.node] = c.m;
@@ -930,7 +971,7 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
                             const JobDev& J, uint64_t slot, bool own) {
   const uint32_t tid = threadIdx.x;
   constexpr bool leaf = kLeafTask;
-  Node c = make_node(t, J, P.start, P.cap_shift);
+  Node c = make_node(t, J, P.start, P.cap_shift, kMode == kSearchFilter ? 0u : P.rotation_lookup);
   stage_keys(t, J, c, s_keys, &sh.na);
   __syncthreads();
   if (leaf) c.na = uni(sh.na);
@@ -1021,7 +1062,7 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
       run_split_filtered(s_keys, c, sh.first, sh.rounds, patience(c, tau), &sh.best,
                          s_keys + split_queue_at(c.m) + (tid >> 6) * 3 * kLeafQueue);
     else
-      eval_chunk(s_keys, c, sh.first, sh.rounds, &sh.best);
+      eval_chunk<kMode != kSearchFilter>(s_keys, c, sh.first, sh.rounds, &sh.best);
     __syncthreads();  // the chunk's best is final; every thread has read the decision
     if (tid == 0) {
       const uint64_t v = sh.best;
@@ -1122,6 +1163,153 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       }
     }
     run_leaf<kMode == kSearchFilter>(P, sh, s_keys, t, J, slot);
+  }
+}
+
+// ---------------------------------------------------------------- one wave per bucket
+// Whole-bucket mode with one wave per worker (workgroups of 64 threads).
+// Where leaves and buckets are small, a node's search usually ends within
+// its first 64 attempts, so four waves sharing one node (256 attempts a
+// round) mostly evaluate attempts above its value.  Here each wave takes
+// bucket roots from the queue in turn (all of them are queued before the
+// launch) and builds each tree alone in its own LDS, 64 attempts a round:
+// the lowest valid lane of the first round with one is the node's value.
+template <typename RoundFn>
+__device__ __forceinline__ uint64_t wave_search(const uint64_t* keys, const Node& c, RoundFn fn) {
+  const uint64_t rounds = c.cap / 64 + 1;
+  for (uint64_t r = 0; r < rounds; ++r) {
+    const uint64_t v = fn(keys, c, r * 64);
+    if (v != kInf) return v;
+  }
+  return kInf;
+}
+
+__device__ uint64_t wave_eval(const uint64_t* keys, const Node& c) {
+  switch (c.kind) {
+    case kLeaf:
+      return c.rotation ? wave_search(keys, c, round_leaf_rot<true>)
+                        : wave_search(keys, c, round_leaf_brute);
+    case kLower:
+    case kUpper:
+      return c.full ? wave_search(keys, c, round_split_kway<true>)
+                    : wave_search(keys, c, round_split_kway<false>);
+    default: return wave_search(keys, c, round_split_binary);
+  }
+}
+
+__device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t, const JobDev& J) {
+  const uint32_t lane = lane_id();
+  const uint32_t cap = P.stage_cap;
+  Frame* stack = reinterpret_cast<Frame*>(lds);
+  uint64_t* s_keys = lds + kBucketStackBytes / sizeof(uint64_t);
+  uint64_t* s_tmp = s_keys + cap;
+  uint8_t* s_cls = reinterpret_cast<uint8_t*>(s_tmp + cap);
+  uint8_t* s_ctmp = s_cls + cap;
+  const Key* src = J.keys[0] + t.key_off;
+  for (uint32_t i = lane; i < t.m; i += 64) {
+    const Key k = src[i];
+    s_keys[i] = k.w1;
+    s_cls[i] = (uint8_t)(k.w0 & 1u);
+  }
+  // the stack's contents are uniform: every lane pushes and pops alike, lane
+  // 0 writes
+  Frame root;
+  root.off = 0;
+  root.m = t.m;
+  root.depth = t.depth;
+  root.pad = 0;
+  root.node = t.node;
+  if (lane == 0) stack[0] = root;
+  uint32_t sp = 1, done = 0;
+  while (sp) {
+    __syncthreads();  // one wave: orders the keys and the stack in LDS
+    if (ld_relaxed(&P.ctl->error) != 0) break;
+    const Frame f = stack[--sp];
+    Task nt;
+    nt.key_off = uni(f.off);
+    nt.m = uni(f.m);
+    nt.depth = (uint16_t)uni(f.depth);
+    nt.node = uni64(f.node);
+    nt.job = t.job;
+    uint64_t* keys = s_keys + nt.key_off;
+    uint8_t* cls = s_cls + nt.key_off;
+    Node c = make_node(nt, J, P.start, P.cap_shift, P.rotation_lookup);
+    if (c.kind == kLeaf) {
+      // the keys of A (class bit clear) first, in a stable order
+      const bool v = lane < c.m;
+      const uint64_t w = v ? keys[lane] : 0;
+      const bool isb = v && cls[lane];
+      const uint64_t bm = __ballot(isb);
+      const uint64_t am = __ballot(v && !isb);
+      c.na = (uint32_t)__popcll(am);
+      const uint64_t below = mask_below(lane);
+      __syncthreads();
+      if (v) keys[isb ? c.na + (uint32_t)__popcll(bm & below) : (uint32_t)__popcll(am & below)] = w;
+      __syncthreads();
+    }
+    const uint64_t v = wave_eval(keys, c);
+    if (v == kInf) {
+      if (lane == 0 && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
+        record_failure(P.ctl, nt, kNoSlot, P.states, 0);
+      break;
+    }
+    if (c.kind != kLeaf) {
+      __syncthreads();
+      partition_lds(P, c, v, keys, cls, s_tmp + nt.key_off, s_ctmp + nt.key_off);
+    }
+    if (lane == 0) {
+      J.vals[nt.node] = v;
+      J.msz[nt.node] = c.m;
+    }
+    ++done;
+    if (c.kind != kLeaf) {
+      // children that store a node (any order: a node's index fixes where its
+      // value goes)
+      uint64_t cn = nt.node + 1;
+      for (uint32_t j = 0; j < c.k; ++j) {
+        const uint32_t sz = j + 1 < c.k ? c.unit : c.last;
+        if (sz >= 2) {
+          if (sp >= kFrames || nt.depth + 1 >= kMaxDepth) {
+            if (lane == 0) set_error(P.ctl, (uint32_t)(-RS_ERR_UNSUPPORTED));
+            sp = 0;
+            break;
+          }
+          Frame g;
+          g.off = (uint32_t)nt.key_off + j * c.unit;
+          g.m = sz;
+          g.depth = nt.depth + 1u;
+          g.pad = 0;
+          g.node = cn;
+          if (lane == 0) stack[sp] = g;
+          ++sp;
+        }
+        cn += uni(J.nodecnt[sz]);
+      }
+    }
+  }
+  if (lane == 0 && done)
+    __hip_atomic_fetch_add(&P.ctl->finished, (uint64_t)done, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+}
+
+__device__ void wave_main(const SearchParams& P) {
+  extern __shared__ uint64_t lds[];
+  const uint32_t lane = lane_id();
+  for (;;) {
+    uint64_t q = 0;
+    if (lane == 0)
+      q = __hip_atomic_fetch_add(&P.ctl->head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    q = uni64(readlane64(q, 0));
+    // every root was queued before the launch (tail is final)
+    if (q >= uni64(ld_relaxed(&P.ctl->tail)) || ld_relaxed(&P.ctl->error) != 0) break;
+    Task t = P.tasks[q];
+    t.key_off = uni64(t.key_off);
+    t.node = uni64(t.node);
+    t.m = uni(t.m);
+    t.depth = (uint16_t)uni(t.depth);
+    t.job = (uint16_t)uni(t.job);
+    wave_bucket(P, lds, t, P.jobs[t.job]);
   }
 }
 
@@ -1259,22 +1447,56 @@ extern "C" __global__ void __launch_bounds__(rs::kWG) rs_bucket_kernel(rs::Searc
   rs::search_main<rs::kSearchBucket>(P);
 }
 
+extern "C" __global__ void __launch_bounds__(64) rs_wave_bucket_kernel(rs::SearchParams P) {
+  rs::wave_main(P);
+}
+
 namespace rs {
 
 static const void* search_kernel(uint32_t mode) {
-  return mode == kSearchBucket   ? reinterpret_cast<const void*>(rs_bucket_kernel)
-         : mode == kSearchFilter ? reinterpret_cast<const void*>(rs_filter_kernel)
-                                 : reinterpret_cast<const void*>(rs_search_kernel);
+  return mode == kSearchBucketWave ? reinterpret_cast<const void*>(rs_wave_bucket_kernel)
+         : mode == kSearchBucket   ? reinterpret_cast<const void*>(rs_bucket_kernel)
+         : mode == kSearchFilter   ? reinterpret_cast<const void*>(rs_filter_kernel)
+                                   : reinterpret_cast<const void*>(rs_search_kernel);
+}
+
+uint32_t search_block(uint32_t mode) { return mode == kSearchBucketWave ? 64u : kWG; }
+
+void rotation_tables(uint16_t* out) {
+  out[0] = out[1] = 0;
+  for (uint32_t m = 1; m <= kRotLookupMaxM; ++m) {
+    const uint32_t full = (1u << m) - 1u;
+    for (uint32_t x = 0; x <= full; ++x) {
+      uint32_t best = x, t = 0, period = m;
+      for (uint32_t r = 1; r < m; ++r) {
+        const uint32_t y = ((x << r) | (x >> (m - r))) & full;
+        if (y < best) {
+          best = y;
+          t = r;
+        }
+        if (y == x && period == m) period = r;
+      }
+      out[(1u << m) + x] = (uint16_t)(t | (period << 8));
+    }
+  }
+}
+
+hipError_t upload_rotation_tables() {
+  std::vector<uint16_t> t(kRotLookupEntries);
+  rotation_tables(t.data());
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_rot_lookup), t.data(), kRotLookupEntries * sizeof(uint16_t),
+                           0, hipMemcpyHostToDevice);
 }
 
 hipError_t search_occupancy(uint32_t lds_bytes, int* blocks_per_cu, uint32_t mode) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel(mode), kWG,
-                                                      lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel(mode),
+                                                      search_block(mode), lds_bytes);
 }
 
 hipError_t launch_search(const SearchParams& p, uint32_t grid, uint32_t lds_bytes, hipStream_t s) {
   void* args[] = {const_cast<SearchParams*>(&p)};
-  return hipLaunchKernel(search_kernel(p.mode), dim3(grid), dim3(kWG), args, lds_bytes, s);
+  return hipLaunchKernel(search_kernel(p.mode), dim3(grid), dim3(search_block(p.mode)), args,
+                         lds_bytes, s);
 }
 
 }  // namespace rs

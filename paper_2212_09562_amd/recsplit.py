@@ -88,6 +88,8 @@ class Job(ctypes.Structure):
 _lib.rs_build_batch.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(_vp),
                                 ctypes.POINTER(ctypes.c_int)]
 _lib.rs_calibrate_valu.argtypes = [ctypes.POINTER(ValuRates)]
+_lib.rs_rotation_lookup.argtypes = [_u32, _u32, _u32]
+_lib.rs_rotation_lookup.restype = ctypes.c_uint32
 _lib.rs_attempt_work.argtypes = [_u32, _u32, _u32]
 _lib.rs_attempt_work.restype = ctypes.c_double
 
@@ -99,7 +101,8 @@ class Schedule(ctypes.Structure):
                                                 "small_tasks_per_worker", "bucket_mode_max_leaf",
                                                 "stall_guard_us", "max_workers",
                                                 "leaf_filter_tau", "join_leaf_tau",
-                                                "split_filter_tau")]
+                                                "split_filter_tau", "rotation_lookup",
+                                                "bucket_wave")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -373,3 +376,12 @@ def calibrate_valu() -> dict:
     r = ValuRates()
     _check(_lib.rs_calibrate_valu(ctypes.byref(r)), "rs_calibrate_valu")
     return r.as_dict()
+
+
+def rotation_lookup(m: int, a: int, b: int) -> int:
+    """rs_rotation_lookup: the smallest rotation r with a | rot_m^r(b) filling
+    all m bits, found by table lookups (host only); m when none fits."""
+    r = _lib.rs_rotation_lookup(m, a, b)
+    if r == 0xFFFFFFFF:
+        raise RecSplitError(-1, "rs_rotation_lookup")
+    return r

@@ -4,10 +4,13 @@ Every job's result must be the same bytes as its solo build and as the
 oracle's; a job that fails (duplicate keys, arguments out of range) reports
 its own code and leaves the others untouched.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
 import oracle
+from oracle import shards
 from paper_2212_09562_amd import keygen
 
 pytestmark = pytest.mark.gpu
@@ -21,6 +24,17 @@ def rs():
 
 def _case(msg):
     print(f"[case] {msg}", flush=True)
+
+
+def _bucket_sizes(keys, nb):
+    """Keys per bucket, bucket = floor(w0 * nb / 2^64) from 32-bit halves
+    (exact for nb < 2^31); used only to pick buckets for the oracle, which
+    reports each bucket's size itself."""
+    w0 = keys[:, 0]
+    hi, lo = w0 >> np.uint64(32), w0 & np.uint64(0xFFFFFFFF)
+    nbu = np.uint64(nb)
+    bucket = (hi * nbu + ((lo * nbu) >> np.uint64(32))) >> np.uint64(32)
+    return np.bincount(bucket.astype(np.int64), minlength=nb)
 
 
 def test_mixed_batch_matches_solo_and_oracle():
@@ -63,8 +77,9 @@ def test_mixed_batch_matches_solo_and_oracle():
 def test_batched_configuration_same_as_solo():
     """The 64-set batch (sizes log-uniform in [10^3, 10^6], l in {8,12,16}, b in
     {100,500,2000}, seed 4): every set's bytes equal its solo build, the ranks of
-    every set form a permutation, and the oracle agrees on the small sets and on
-    sampled buckets of the large ones."""
+    every set form a permutation, and the oracle agrees on the small sets and,
+    bucket by bucket (node values and Golomb-Rice records), on the largest
+    bucket of every large set and the first and last of most of them."""
     import torch
 
     jobs = keygen.batched_jobs(64, seed=4)
@@ -73,7 +88,7 @@ def test_batched_configuration_same_as_solo():
               "bucket_size": j["bucket_size"], "keep_values": True} for j in jobs]
     outs, st = rs().build_batch(batch)
     assert all(s == 0 for s in st), st
-    sampled = 0
+    checks = []  # (set, buckets) the oracle rebuilds from the large sets
     for i, j in enumerate(jobs):
         data = outs[i].serialize()
         solo = rs().build(batch[i]["keys"], j["leaf_size"], j["bucket_size"], True).serialize()
@@ -84,11 +99,35 @@ def test_batched_configuration_same_as_solo():
             (j["leaf_size"] == 12 and j["n"] <= 20000) or j["n"] <= 2000
         if cheap:
             assert data == oracle.build(j["keys"], j["leaf_size"], j["bucket_size"], True)[0], i
-        elif sampled < 4 and j["bucket_size"] <= 500:
-            sampled += 1
-            recs, _ = oracle.build_buckets(j["keys"], j["leaf_size"], j["bucket_size"], True, [0])
-            for (bk, size, vals, words, nbits) in recs:
-                assert np.array_equal(outs[i].node_values(bk), vals), (i, bk)
+        else:
+            # the largest bucket of every large set (one bucket of the l = 16,
+            # b = 2000 sets, whose buckets cost the oracle seconds each), and
+            # the first and last of the others
+            nb = oracle.num_buckets(j["n"], j["bucket_size"])
+            sizes = _bucket_sizes(j["keys"], nb)
+            sel = {int(np.argmax(sizes))}
+            if not (j["leaf_size"] == 16 and j["bucket_size"] == 2000):
+                sel |= {0, nb - 1}
+            checks.append((i, sorted(sel)))
+    _case(f"oracle on {sum(len(c[1]) for c in checks)} buckets of {len(checks)} large sets")
+
+    def rebuild(check):
+        i, sel = check
+        j = jobs[i]
+        res, _ = shards.build_buckets_parallel(j["keys"], j["leaf_size"], j["bucket_size"], True,
+                                               sel, procs=len(sel))
+        return i, res
+
+    with ThreadPoolExecutor(max_workers=max(1, shards.host_cores() // 2)) as ex:
+        done = list(ex.map(rebuild, checks))
+    assert any(jobs[i]["leaf_size"] == 16 and jobs[i]["bucket_size"] == 2000 for i, _ in done)
+    for i, res in done:
+        data = outs[i].serialize()
+        for bk, (size, vals, words, nbits) in res.items():
+            assert size == _bucket_sizes(jobs[i]["keys"], outs[i].stats()["nb"])[bk], (i, bk)
+            assert np.array_equal(outs[i].node_values(bk), vals), (i, bk)
+            gw, gb = oracle.bucket_record(data, bk)
+            assert gb == nbits and np.array_equal(gw, words), (i, bk)
 
 
 def test_autotuner_runs_and_leaves_defaults():

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import shards
 from paper_2212_09562_amd import keygen
 
 pytestmark = pytest.mark.gpu
@@ -125,12 +126,14 @@ BUCKET_MODE = [(5000, 8, 100, True), (5000, 8, 100, False), (3000, 2, 7, True), 
 
 @pytest.mark.parametrize("n,l,b,rot", BUCKET_MODE)
 def test_whole_bucket_mode(n, l, b, rot):
-    """One worker per bucket, the tree built in LDS (forced with a small grid)."""
+    """One worker per bucket, the tree built in LDS (forced with a small
+    grid), the worker four waves or one."""
     keys = keygen.fingerprints(n, 300 + n + l)
     try:
-        rs().set_schedule(None)
-        rs().set_schedule(max_workers=4, bucket_mode_max_leaf=24)
-        _check_parity(keys, l, b, rot, "whole-bucket workers")
+        for wave in (0, 1):
+            rs().set_schedule(None)
+            rs().set_schedule(max_workers=4, bucket_mode_max_leaf=24, bucket_wave=wave)
+            _check_parity(keys, l, b, rot, f"whole-bucket workers, bucket_wave={wave}")
     finally:
         rs().set_schedule(None)
 
@@ -178,6 +181,31 @@ def test_filtered_split_search(n, l, b, rot):
             rs().set_schedule(None)
             rs().set_schedule(**sched)
             _check_parity(keys, l, b, rot, str(sched))
+    finally:
+        rs().set_schedule(None)
+
+
+LOOKUP = [(5000, 8, 100), (3000, 4, 30), (20000, 12, 1000), (6000, 10, 60), (2500, 16, 2000),
+          (1500, 5, 1), (4000, 6, 7), (3000, 14, 500), (2000, 2, 3)]
+
+
+@pytest.mark.parametrize("n,l,b", LOOKUP)
+def test_rotation_lookup_tables(n, l, b):
+    """Rotation-fitting leaves that find their rotation by table lookups
+    (Sec. 4 "Lookup Tables"; rotation_lookup=1): in the plain kernel with
+    node tasks, in whole-bucket workers, and with the filters on (whose
+    kernel keeps the wave test): the oracle's bytes every time."""
+    keys = keygen.fingerprints(n, 1100 + n + l)
+    try:
+        for sched in ({"rotation_lookup": 1, "bucket_mode_max_leaf": 0, "leaf_filter_tau": 0,
+                       "split_filter_tau": 0},
+                      {"rotation_lookup": 1, "max_workers": 4, "bucket_mode_max_leaf": 24},
+                      {"rotation_lookup": 1, "max_workers": 4, "bucket_mode_max_leaf": 24,
+                       "bucket_wave": 0},
+                      {"rotation_lookup": 1}):
+            rs().set_schedule(None)
+            rs().set_schedule(**sched)
+            _check_parity(keys, l, b, True, str(sched))
     finally:
         rs().set_schedule(None)
 
@@ -326,8 +354,9 @@ def _parse_offsets(data):
 
 def test_config_l16_b2000_sampled():
     """10^7 keys, l=16, b=2000, rotation fitting: the whole build on the GPU,
-    checked on a sample of buckets rebuilt by the oracle (values and their
-    Golomb-Rice records), on the bucket sizes, and on the ranks of all keys."""
+    checked on 48 buckets rebuilt by the oracle (values and their Golomb-Rice
+    records; the largest and smallest bucket among them), on the bucket sizes,
+    and on the ranks of all keys."""
     import torch
 
     n, l, b = 10_000_000, 16, 2000
@@ -340,9 +369,20 @@ def test_config_l16_b2000_sampled():
     C, P, gr_off, words = _parse_offsets(data)
     bucket = ((keys[:, 0].astype(object) * nb) >> 64).astype(np.int64)
     assert np.array_equal(np.diff(C.astype(np.int64)), np.bincount(bucket, minlength=nb))
-    sel = [0, 2500, nb - 1]
-    recs, st = oracle.build_buckets(keys, l, b, True, sel)
-    for (j, size, vals, rec_words, rec_bits) in recs:
+    # 48 buckets the oracle rebuilds, one single-threaded oracle process per
+    # host core: the largest and the smallest bucket, the first and the last,
+    # and 44 spread evenly over the rest
+    sizes = np.bincount(bucket, minlength=nb)
+    sel = {0, nb - 1, int(np.argmax(sizes)), int(np.argmin(sizes))}
+    for j in np.linspace(1, nb - 2, 60).astype(int):
+        if len(sel) == 48:
+            break
+        sel.add(int(j))
+    assert len(sel) == 48
+    res, _ = shards.build_buckets_parallel(keys, l, b, True, sorted(sel))
+    assert sorted(res) == sorted(sel)
+    for j, (size, vals, rec_words, rec_bits) in sorted(res.items()):
+        assert size == sizes[j], j
         assert np.array_equal(f.node_values(j), vals), j
         assert int(P[j + 1] - P[j]) == rec_bits
         assert np.array_equal(_record_bits(words, gr_off, int(P[j]), rec_bits), rec_words), j

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import shards
 from paper_2212_09562_amd import keygen
 
 pytestmark = pytest.mark.gpu
@@ -75,6 +76,23 @@ def test_server_mix_equals_alone():
         if i % 5 == 0:
             ranks = f.query(r["keys"])
             assert np.array_equal(np.sort(ranks), np.arange(r["n"], dtype=np.uint64))
+    # the three largest requests, bucket by bucket against the oracle (node
+    # values and Golomb-Rice records of the served bytes): the first, the
+    # last and three more buckets of each, one oracle process per bucket
+    largest = sorted(range(len(reqs)), key=lambda i: -reqs[i]["n"])[:3]
+    assert all(reqs[i]["n"] > 20000 for i in largest)
+    for i in largest:
+        r, (f, _, _) = reqs[i], results[i]
+        nb = oracle.num_buckets(r["n"], r["b"])
+        sel = sorted({0, nb // 4, nb // 2, 3 * nb // 4, nb - 1})
+        _case(f"oracle on buckets {sel} of a served request of {r['n']} keys (l={r['l']})")
+        res, _ = shards.build_buckets_parallel(r["keys"], r["l"], r["b"], True, sel)
+        data = f.serialize()
+        assert sorted(res) == sel
+        for bk, (size, vals, words, nbits) in res.items():
+            assert np.array_equal(oracle.bucket_values(data, bk), vals), (i, bk)
+            gw, gb = oracle.bucket_record(data, bk)
+            assert gb == nbits and np.array_equal(gw, words), (i, bk)
 
 
 def test_server_budget_admission_and_errors():
