@@ -82,6 +82,41 @@ int rs_build(const rs_key128 *keys, uint64_t n, uint32_t leaf_size, uint32_t buc
              uint32_t flags, rs_mphf **out);
 
 /*
+ * rs_build for callers that cannot allocate device memory: code that must not
+ * call hipMalloc or hipFree (tight serving loops, harnesses that forbid
+ * allocation).  The build's working memory -- staged and sorted keys, bucket
+ * sizes and offsets, node values, the search's task queue, states and
+ * counters, and the encoded words before they are copied out -- lies in one
+ * device array of RS_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends (the same array holds the
+ * starting seeds and the per-leaf-size tables every entry point reads).  This
+ * call makes no hipMalloc, hipFree or other device or pinned-host allocation.
+ *
+ * keys, n, leaf_size, bucket_size, flags: as rs_build, with
+ *   n <= RS_NOALLOC_MAX_KEYS; n above it, or RS_FLAG_KEEP_VALUES, is refused
+ *   with RS_ERR_INVALID_ARG before any device work.
+ * words:  caller-owned host buffer of cap_words 64-bit words (cap_words >= 1)
+ *         that receives the serialised structure, word for word what
+ *         rs_serialize gives for rs_build of the same arguments.
+ * nwords: receives the number of words written.  When the structure needs
+ *         more than cap_words, nothing is written to words, *nwords receives
+ *         the count needed and the call returns RS_ERR_INVALID_ARG (call
+ *         again with a larger buffer; the result will be the same).
+ * The array keeps the last call's contents; a call clears everything it
+ * needs cleared.  Calls on one device share the array and would race, so
+ * the library serialises them with a lock (a second caller waits); calls on
+ * different devices, or from different processes, use different copies.
+ * Other errors as rs_build; RS_ERR_OOM if the encoded words do not fit the
+ * space left after the working memory (at least 8 MiB; never reached by
+ * structures of 2 bits per key).
+ */
+#define RS_NOALLOC_MAX_KEYS (1u << 19)
+#define RS_NOALLOC_SCRATCH_BYTES (128ull << 20)
+
+int rs_build_noalloc(const rs_key128 *keys, uint64_t n, uint32_t leaf_size, uint32_t bucket_size,
+                     uint32_t flags, uint64_t *words, uint64_t cap_words, uint64_t *nwords);
+
+/*
  * Build many independent key sets at once.  Each job is what rs_build takes;
  * the buckets of all jobs are sorted job by job, then every node of every job
  * is searched by one persistent launch (one device work queue), then every

@@ -37,7 +37,7 @@ constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign;
 // device_get asks for its device address with hipGetSymbolAddress once per
 // device, with that device current, and every use goes through
 // Device::scratch.
-constexpr size_t kScratchBytes = 128ull << 20;
+constexpr size_t kScratchBytes = RS_NOALLOC_SCRATCH_BYTES;
 constexpr size_t kSeedBytes = 4096;
 constexpr size_t kTableSlot = 3 * align_up(kTable * sizeof(uint32_t)) + align_up(kTable);
 constexpr size_t kNoAllocAt = kSeedBytes + (kMaxLeaf + 1) * kTableSlot;
@@ -50,10 +50,10 @@ static __device__ __align__(256) uint64_t scratch[kScratchBytes / sizeof(uint64_
 // flag; plus 1 MiB for the scan space, counters and worker table.  The
 // encoded words take what is left (at least 8 MiB: several hundred bits per
 // key, against the 1.5 to 2 bits per key that builds need).
-constexpr size_t kNoAllocWorkBound = (size_t)((1u << 19) + 2) * 168 + (1u << 20);
+constexpr size_t kNoAllocWorkBound = (size_t)(RS_NOALLOC_MAX_KEYS + 2) * 168 + (1u << 20);
 static_assert(kSeedBytes >= kMaxDepth * sizeof(uint64_t), "seed space");
 static_assert(kNoAllocAt + kNoAllocWorkBound + (8u << 20) <= kScratchBytes,
-              "fixed array too small for 2^19 keys");
+              "fixed array too small for RS_NOALLOC_MAX_KEYS keys");
 
 int from_hip(hipError_t e) {
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return RS_ERR_OOM;
@@ -303,6 +303,8 @@ int device_get(Device** out) {
     d.start = reinterpret_cast<uint64_t*>(d.scratch);
     HIPCHECK(hipMemcpy(d.start, h, sizeof h, hipMemcpyHostToDevice));
     HIPCHECK(upload_rotation_tables());
+    int rc = context_init(d.noalloc, &d);
+    if (rc) return rc;
     d.ready = true;
   }
   *out = &d;
@@ -978,6 +980,44 @@ int rs_build(const rs_key128* keys, uint64_t n, uint32_t leaf_size, uint32_t buc
   if (plan[0].status) return plan[0].status;
   *out = plan[0].out;
   return RS_OK;
+}
+
+int rs_build_noalloc(const rs_key128* keys, uint64_t n, uint32_t leaf_size, uint32_t bucket_size,
+                     uint32_t flags, uint64_t* words, uint64_t cap_words, uint64_t* nwords) {
+  if (!nwords) return RS_ERR_INVALID_ARG;
+  *nwords = 0;
+  if (!job_args_ok(keys, n, leaf_size, bucket_size, flags) || (flags & RS_FLAG_KEEP_VALUES) ||
+      n > RS_NOALLOC_MAX_KEYS || !words || !cap_words)
+    return RS_ERR_INVALID_ARG;
+  Device* d = nullptr;
+  int rc = device_get(&d);
+  if (rc) return rc;
+  Context& c = d->noalloc;
+  std::lock_guard<std::mutex> lock(c.mu);
+  std::vector<JobPlan> plan(1);
+  JobPlan& j = plan[0];
+  j.keys = reinterpret_cast<const Key*>(keys);
+  j.n = n;
+  j.l = leaf_size;
+  j.b = bucket_size;
+  j.flags = flags;
+  j.host_words = words;
+  j.host_cap = cap_words;
+  // working memory, then the encoded words, in the fixed array after the
+  // seeds and tables
+  const size_t work = batch_footprint(plan, max_workers(*d));
+  if (work > kNoAllocWorkBound) return RS_ERR_INVALID_ARG;
+  const size_t out_at = align_up(kNoAllocAt + work);
+  j.dev_words = reinterpret_cast<uint64_t*>(d->scratch + out_at);
+  j.dev_cap = (kScratchBytes - out_at) / sizeof(uint64_t);
+  rc = build_jobs(c, plan, d->scratch + kNoAllocAt, work, 0);
+  if (rc) {
+    (void)hipStreamSynchronize(c.s);
+    (void)hipGetLastError();
+    return rc;
+  }
+  *nwords = j.nwords;
+  return j.status;
 }
 
 int rs_build_batch(const rs_job* jobs, uint32_t njobs, rs_mphf** outs, int* statuses) {

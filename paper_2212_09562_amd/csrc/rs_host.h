@@ -56,6 +56,7 @@ struct Device {
   uint64_t* start = nullptr;  // starting seed of depth d: SplitMix64(0) output d+1
   Tables tables[kMaxLeaf + 1];
   std::mutex mu;  // guards lazy initialisation of the tables
+  Context noalloc;
 };
 
 int device_get(Device** out);

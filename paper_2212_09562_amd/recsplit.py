@@ -26,6 +26,7 @@ RS_FLAG_ROTATION = 1
 RS_FLAG_KEYS_ON_DEVICE = 2
 RS_FLAG_KEEP_VALUES = 4
 RS_PENDING = 1
+RS_NOALLOC_MAX_KEYS = 1 << 19
 
 ERRORS = {0: "RS_OK", -1: "RS_ERR_INVALID_ARG", -2: "RS_ERR_DUPLICATE", -3: "RS_ERR_OOM",
           -4: "RS_ERR_DEVICE", -5: "RS_ERR_CORRUPT", -6: "RS_ERR_SEARCH_LIMIT",
@@ -73,6 +74,7 @@ _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
 _u32 = ctypes.c_uint32
 _lib.rs_build.argtypes = [_vp, _u64, _u32, _u32, _u32, ctypes.POINTER(_vp)]
+_lib.rs_build_noalloc.argtypes = [_vp, _u64, _u32, _u32, _u32, _vp, _u64, ctypes.POINTER(_u64)]
 _lib.rs_query.argtypes = [_vp, _vp, _u64, _vp, _u32]
 _lib.rs_serialize.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64)]
 _lib.rs_deserialize.argtypes = [_vp, _u64, ctypes.POINTER(_vp)]
@@ -146,7 +148,7 @@ _lib.rs_free.argtypes = [_vp]
 _lib.rs_free.restype = None
 _lib.rs_strerror.argtypes = [ctypes.c_int]
 _lib.rs_strerror.restype = ctypes.c_char_p
-for _f in ("rs_build", "rs_build_batch", "rs_query", "rs_serialize", "rs_deserialize",
+for _f in ("rs_build", "rs_build_noalloc", "rs_build_batch", "rs_query", "rs_serialize", "rs_deserialize",
            "rs_debug_node_values", "rs_get_stats", "rs_calibrate_valu", "rs_server_create",
            "rs_server_submit", "rs_server_poll", "rs_server_get_stats", "rs_set_schedule",
            "rs_get_schedule"):
@@ -248,6 +250,29 @@ def build(keys, leaf_size: int, bucket_size: int, rotation: bool = True,
     h = ctypes.c_void_p()
     _check(_lib.rs_build(ptr, n, leaf_size, bucket_size, flags, ctypes.byref(h)), "rs_build")
     return MPHF(h.value)
+
+
+def build_noalloc(keys, leaf_size: int, bucket_size: int, rotation: bool = True,
+                  cap_words: int | None = None) -> bytes:
+    """rs_build_noalloc: the serialised structure (the bytes build(...).serialize()
+    gives) built in the library's fixed device array, for callers that may not
+    allocate device memory; at most RS_NOALLOC_MAX_KEYS keys.  cap_words sizes
+    the host output buffer (default: room for 8 bits per key); a structure that
+    needs more is built again into a buffer of the size the library reports."""
+    ptr, n, flags, keep = _keys_arg(keys)
+    flags |= RS_FLAG_ROTATION if rotation else 0
+    cap = cap_words if cap_words is not None else 64 + n // 8 + 4 * (n // max(bucket_size, 1))
+    for _ in range(2):
+        out = np.zeros(max(int(cap), 1), dtype=np.uint64)
+        nw = ctypes.c_uint64()
+        rc = _lib.rs_build_noalloc(ptr, n, leaf_size, bucket_size, flags, out.ctypes.data,
+                                   len(out), ctypes.byref(nw))
+        if rc == -1 and nw.value > len(out):
+            cap = nw.value
+            continue
+        _check(rc, "rs_build_noalloc")
+        return out[:nw.value].tobytes()
+    raise RecSplitError(-1, "rs_build_noalloc")
 
 
 def build_batch(jobs):

@@ -132,3 +132,29 @@ def test_query_output_tensor_checked_before_the_library_is_called():
     for out, exc in bad:
         with pytest.raises(exc):
             recsplit._check_out(out, 10, cpu)
+
+
+def test_noalloc_refuses_oversized_builds_before_any_device_call():
+    import ctypes
+
+    import numpy as np
+
+    from paper_2212_09562_amd import recsplit
+
+    lib = recsplit.library()
+    keys = np.zeros((4, 2), dtype=np.uint64)
+    words = np.zeros(64, dtype=np.uint64)
+    nw = ctypes.c_uint64(123)
+    # one key above the maximum (the keys are not read: the size is refused first)
+    rc = lib.rs_build_noalloc(keys.ctypes.data, recsplit.RS_NOALLOC_MAX_KEYS + 1, 8, 100,
+                              recsplit.RS_FLAG_ROTATION, words.ctypes.data, len(words),
+                              ctypes.byref(nw))
+    assert rc == -1 and nw.value == 0
+    rc = lib.rs_build_noalloc(keys.ctypes.data, 4, 8, 100, recsplit.RS_FLAG_KEEP_VALUES,
+                              words.ctypes.data, len(words), ctypes.byref(nw))
+    assert rc == -1
+    rc = lib.rs_build_noalloc(keys.ctypes.data, 4, 8, 100, 0, None, 0, ctypes.byref(nw))
+    assert rc == -1
+    hdr = open(os.path.join(ROOT, "include", "recsplit.h")).read()
+    assert "#define RS_NOALLOC_MAX_KEYS (1u << 19)" in hdr
+    assert recsplit.RS_NOALLOC_MAX_KEYS == 1 << 19
