@@ -469,6 +469,9 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--per-launch", type=int, default=8)
     ap.add_argument("--reserve-per-cu", type=int, default=1)
+    ap.add_argument("--served-only", action="store_true",
+                    help="instead: only the served workload (with --budget-gib, --slots, "
+                         "--per-launch, --reserve-per-cu)")
     ap.add_argument("--sweep", action="store_true",
                     help="instead: leaf size x bucket size x leaf method sweep on 10^6 keys")
     ap.add_argument("--single", nargs=3, type=int, metavar=("L", "B", "N"), action="append",
@@ -502,6 +505,11 @@ def main():
         return
     if args.calibrate:
         print(json.dumps({"valu_rates": recsplit.calibrate_valu()}), flush=True)
+        return
+    if args.served_only:
+        print(json.dumps({"served": run_served(recsplit, keygen, torch, args.served_requests,
+                                               args.budget_gib, args.slots, args.per_launch,
+                                               args.reserve_per_cu)}), flush=True)
         return
     if args.single:
         for l, b, n in args.single:

@@ -226,10 +226,13 @@ void rs_server_destroy(rs_server *s);
  *   inline_leaf_tau_*: a leaf child whose Rice parameter is below this is
  *                   searched by the worker that split its parent, right after
  *                   the split, instead of going through the queue (0: never)
- *   bucket_mode_max_leaf: a launch whose leaf sizes are all at most this,
- *                   whose buckets hold at most 1152 keys and number at least
- *                   four per worker is run with one worker per bucket, the
- *                   whole bucket tree built in LDS (0: never)
+ *   bucket_mode_max_leaf: a launch whose leaf sizes are all at most this
+ *                   and whose buckets hold at most 1152 keys is run with one
+ *                   worker per bucket, the whole bucket tree built in LDS,
+ *                   when the buckets number at least four per four-wave
+ *                   worker, or with bucket_wave also when they number at
+ *                   least one per four-wave worker or hold at most 256 keys
+ *                   each (0: never)
  *   stall_guard_us: a search launch in which no node finishes for this
  *                   long is stopped with RS_ERR_DEVICE (a bug guard; 0: ten
  *                   seconds)

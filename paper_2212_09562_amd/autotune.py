@@ -2,8 +2,10 @@
 
 The schedule decides how the persistent search kernel hands out attempts --
 the chunk length of a split search relative to its expected length, how
-soon idle workers join a long search, the grid size -- and never what it
-finds: every schedule yields the same structure.  Small launches (few nodes
+soon idle workers join a long search, the grid size, the bucket-to-workgroup
+mapping of small trees (one wave and 64 seeds a round, or four waves and
+256), how a rotation is fitted -- and never what it finds: every schedule
+yields the same structure.  Small launches (few nodes
 per worker, e.g. one small request) are latency bound and want short chunks
 that idle workers share early; large launches are throughput bound and want
 few claims (little scheduling traffic) as long as that costs no time.
@@ -34,6 +36,11 @@ SHIFTS = (10, 12, 13, 14, 15, 16, 63)
 HELP_AFTER = (1, 4, 16, 64)
 INLINE_TAU = (0, 10, 13, 16, 20)
 BUCKET_LEAF = (0, 8, 10, 12)
+# bucket-to-workgroup mapping in whole-bucket mode: 0 = four waves share a
+# bucket (256 seeds per round), 1 = one wave per bucket (64 seeds per round)
+BUCKET_WAVE = (0, 1)
+# rotation leaves: 0 = the wave tests every rotation, 1 = two table lookups
+ROTATION_LOOKUP = (0, 1)
 
 
 def _time_sets(sets, keys, reps, ref=None):
@@ -53,11 +60,15 @@ def _time_sets(sets, keys, reps, ref=None):
 
 
 def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, shifts=SHIFTS, help_after=HELP_AFTER,
-         inline_tau=INLINE_TAU, bucket_leaf=BUCKET_LEAF, reps=3, seed=11, tol=0.01, log=None):
+         inline_tau=INLINE_TAU, bucket_leaf=BUCKET_LEAF, bucket_wave=BUCKET_WAVE,
+         rotation_lookup=ROTATION_LOOKUP, reps=3, seed=11, tol=0.01, log=None):
     """Per launch class: the fastest (chunk_shift, help_after), then the
     fastest inline_leaf_tau with those; then, on the large sets, the
-    whole-bucket threshold (the smallest within tol of the fastest).  Returns
-    the schedule dict and the timing table."""
+    whole-bucket threshold (the smallest within tol of the fastest), the
+    bucket-to-workgroup mapping (seeds per wave and round) and the rotation
+    test (wave or lookup tables), each kept at its default unless another
+    value is faster by more than tol.  Returns the schedule dict and the
+    timing table."""
     import torch
 
     base = recsplit.set_schedule(None)
@@ -115,6 +126,20 @@ def tune(small_sets=SMALL_SETS, large_sets=LARGE_SETS, shifts=SHIFTS, help_after
                 table["bucket_mode"] = [{"cost": t, "bucket_mode_max_leaf": bl} for t, bl in results]
                 low = min(t for t, _ in results)
                 best["bucket_mode_max_leaf"] = min(bl for t, bl in results if t <= low * (1.0 + tol))
+                for name, values in (("bucket_wave", bucket_wave),
+                                     ("rotation_lookup", rotation_lookup)):
+                    results = []
+                    for v in values:
+                        recsplit.set_schedule(best, **force, **{name: v})
+                        t = _time_sets(sets, ks, reps, ref)
+                        results.append((t, v))
+                        if log:
+                            log(f"{cls} {name}={v}: {t:.4f}")
+                    table[name] = [{"cost": t, name: v} for t, v in results]
+                    at_default = [t for t, v in results if v == base[name]]
+                    low_t, low_v = min(results)
+                    if not at_default or low_t < at_default[0] * (1.0 - tol):
+                        best[name] = low_v
     finally:
         recsplit.set_schedule(None)
     return best, table

@@ -754,17 +754,21 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   }
   if (total >= (1ull << 31) || total > node_cap) return RS_ERR_UNSUPPORTED;
   HIPCHECK(hipEventRecord(c.ev[2], s));
-  // whole-bucket workers for small leaves and small buckets when there are
-  // enough buckets to keep every worker busy
+  // whole-bucket workers for small leaves and small buckets: with four-wave
+  // workers when there are enough buckets to keep every worker busy; with
+  // one-wave workers also when every bucket is small (a tree of a few dozen
+  // nodes built by one wave ends sooner than the same nodes passed between
+  // workers through the queue, level by level)
   bool bucket_mode = sched.bucket_mode_max_leaf != 0 && maxm <= kBucketModeMaxKeys &&
-                     nbk >= 4ull * workers;
+                     (nbk >= 4ull * workers ||
+                      (sched.bucket_wave && (nbk >= workers || maxm <= kWaveBucketSmall)));
   for (const JobPlan& j : jobs)
     if (!j.status && j.l > sched.bucket_mode_max_leaf) bucket_mode = false;
 
   // the filter kernel when split searches are filtered or some job's full
   // leaves reach leaf_filter_tau; LDS for the largest node's keys and for the
   // queues of a filtered leaf or split
-  bool filter = false;
+  bool filter = false, wide = false;
   uint32_t words = maxm < 64 ? 64 : maxm;
   for (const JobPlan& j : jobs) {
     if (j.status || bucket_mode) continue;
@@ -775,6 +779,15 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
                         (rice_parameter(log_success(sh, sh.la)) >= sched.split_filter_tau ||
                          rice_parameter(log_success(sh, sh.ua)) >= sched.split_filter_tau);
     if (leaves || splits) filter = true;
+    // split counters of a full lower or upper node: k-1 fields of the bit
+    // length of the part size; past 31 bits the wide kernel (64-bit words)
+    auto field_bits = [](uint32_t k, uint32_t unit) {
+      uint32_t fe = 0;
+      while ((1u << fe) <= unit) ++fe;
+      return (k - 1) * fe;
+    };
+    if (splits && (field_bits(sh.la / sh.l, sh.l) > 31 || field_bits(sh.ua / sh.la, sh.la) > 31))
+      wide = true;
     if (leaves && words < kLeafFilterWords) words = kLeafFilterWords;
     if (splits) {
       const uint32_t ua = sh.ua;
@@ -783,7 +796,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     }
   }
   const uint32_t mode = bucket_mode ? (sched.bucket_wave ? kSearchBucketWave : kSearchBucket)
-                       : filter    ? kSearchFilter
+                       : filter    ? (wide ? kSearchFilterWide : kSearchFilter)
                                    : kSearchNode;
 
   // 2. seed search over all nodes of all jobs, one persistent launch

@@ -196,13 +196,21 @@ constexpr uint32_t kRotLookupEntries = 2u << kRotLookupMaxM;
 // per key its hashed word, a scratch word, its A/B class and a scratch class.
 constexpr uint32_t kBucketStackBytes = 64 * 24;
 constexpr uint32_t kBucketModeMaxKeys = 1152;  // largest bucket (LDS of 7 workers per CU)
+constexpr uint32_t kWaveBucketSmall = 256;     // one-wave bucket workers whatever the bucket count
 __host__ __device__ inline uint32_t bucket_lds_bytes(uint32_t cap) {
   return kBucketStackBytes + cap * 18u;
 }
 
-// Search kernels: nodes as tasks; the same with filtered leaves; whole
-// buckets per worker of four waves; whole buckets per wave.
-enum : uint32_t { kSearchNode = 0, kSearchFilter = 1, kSearchBucket = 2, kSearchBucketWave = 3 };
+// Search kernels: nodes as tasks; the same with staged (early-exit) leaf and
+// split searches, 32-bit or 64-bit split counters; whole buckets per worker
+// of four waves; whole buckets per wave.
+enum : uint32_t {
+  kSearchNode = 0,
+  kSearchFilter = 1,
+  kSearchBucket = 2,
+  kSearchBucketWave = 3,
+  kSearchFilterWide = 4
+};
 
 struct SearchParams {
   const JobDev* jobs;

@@ -23,6 +23,8 @@
 // within a round a wave takes the lowest lane whose attempt is valid (ballot
 // then count-trailing-zeros); across waves and chunks the minimum is taken
 // with atomicMin, and no chunk that could hold a smaller value is skipped.
+#include <type_traits>
+
 #include "rs_launch.h"
 
 namespace rs {
@@ -33,6 +35,11 @@ constexpr uint64_t kNoSlot = ~0ull;
 constexpr uint64_t kExhausted = ~0ull - 1;
 
 enum : uint32_t { kActExit = 0, kActOwn = 1, kActHelp = 2, kActScan = 3, kActRetry = 4 };
+
+// The kernels with staged (early-exit) searches.
+__host__ __device__ constexpr bool filter_mode(uint32_t mode) {
+  return mode == kSearchFilter || mode == kSearchFilterWide;
+}
 
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(const T* p) {
@@ -451,9 +458,9 @@ __device__ void run_leaf_filtered(const Node& c, uint64_t first, uint32_t rounds
 // A lower or upper split attempt is dead once some child has received more
 // keys than its part size, which usually shows well before the last key
 // (about 17 % fewer evaluations at 112 keys in 7 parts, 5 % at 560 in 5).
-// The same staged scheme as for leaves, with four stages over the keys split
-// at 5/7, 6/7 and 13/14 of m and three queues per wave; an entry is
-// (index << 32) | counters.
+// The same staged scheme as for leaves, with four stages over the keys (the
+// stage ends depend on the node kind, make_split_filter) and three queues
+// per wave; an entry is (index << 32) | counters.
 // Counters: the first k-1 children in fields of fe bits, fe the bit length
 // of the part size, so a field holds its part size without carrying; the
 // last child (its count follows from the total) is added above them and
@@ -464,43 +471,65 @@ __device__ void run_leaf_filtered(const Node& c, uint64_t first, uint32_t rounds
 // is verified exactly before it counts.
 constexpr uint32_t kMinFilterRounds = 8;  // shorter chunks: the plain rounds
 
+// Counter words: 32 bits where the k-1 fields fit (up to l = 18), else 64
+// bits (the wide filter kernel, l = 19 to 24: at most 40 bits of fields).  A
+// queue entry packs the attempt index (below 2^14: at most 256 rounds of 64
+// per chunk and wave) above the counters: (index << 32) | counters, or
+// (index << 50) | the low 50 bits of the counters.
+template <typename T>
 struct SplitFilter {
-  uint32_t fe, target, comp, carries, low, b1, b2, b3;
+  static constexpr uint32_t kIdxShift = sizeof(T) == 4 ? 32u : 50u;
+  static constexpr uint64_t kAccMask = sizeof(T) == 4 ? 0xFFFFFFFFull : (1ull << 50) - 1;
+  uint32_t fe, b1, b2, b3;
+  T target, comp, carries, low;
 };
 
+template <typename T>
 __device__ __forceinline__ bool split_filter_fits(const Node& c) {
   const uint32_t fe = 32u - (uint32_t)__clz(c.unit);
-  return (c.kind == kLower || c.kind == kUpper) && c.k >= 2 && (c.k - 1) * fe <= 31u;
+  return (c.kind == kLower || c.kind == kUpper) && c.k >= 2 &&
+         (c.k - 1) * fe < SplitFilter<T>::kIdxShift;
 }
 
-__device__ __forceinline__ SplitFilter make_split_filter(const Node& c) {
-  SplitFilter f;
+template <typename T>
+__device__ __forceinline__ SplitFilter<T> make_split_filter(const Node& c) {
+  SplitFilter<T> f;
   f.fe = 32u - (uint32_t)__clz(c.unit);
   f.target = f.comp = f.carries = 0;
   for (uint32_t j = 0; j + 1 < c.k; ++j) {
-    f.target |= c.unit << (f.fe * j);
-    f.comp |= ((1u << f.fe) - 1u - c.unit) << (f.fe * j);
-    f.carries |= 1u << (f.fe * (j + 1));
+    f.target |= (T)c.unit << (f.fe * j);
+    f.comp |= (T)((1u << f.fe) - 1u - c.unit) << (f.fe * j);
+    f.carries |= (T)1 << (f.fe * (j + 1));
   }
-  f.low = (1u << (f.fe * (c.k - 1))) - 1u;
-  f.b1 = c.m * 5 / 7;
-  f.b2 = c.m * 6 / 7;
-  f.b3 = c.m * 13 / 14;
+  f.low = ((T)1 << (f.fe * (c.k - 1))) - 1u;
+  // Stage ends, as fractions of m chosen per node kind from the law of the
+  // key at which an attempt dies (simulated for 7 parts of 16 and 5 parts
+  // of 112; a queue hand-off counted as one more key): lower splits die
+  // from about 60 % of their keys on, upper splits only near the end.
+  if (c.kind == kLower) {
+    f.b1 = c.m * 79 / 112;
+    f.b2 = c.m * 89 / 112;
+    f.b3 = c.m * 98 / 112;
+  } else {
+    f.b1 = c.m * 123 / 140;
+    f.b2 = c.m * 257 / 280;
+    f.b3 = c.m * 267 / 280;
+  }
   return f;
 }
 
-__device__ __forceinline__ uint32_t split_count(const uint64_t* keys, const Node& c, uint32_t fe,
-                                                uint32_t lo, uint32_t hi, uint64_t X,
-                                                uint32_t acc) {
+template <typename T>
+__device__ __forceinline__ T split_count(const uint64_t* keys, const Node& c, uint32_t fe,
+                                         uint32_t lo, uint32_t hi, uint64_t X, T acc) {
   if (c.full) {
 #pragma unroll 4
     for (uint32_t i = lo; i < hi; ++i)
-      acc += 1u << __umul24(reduce(hash_top(keys[i], X), c.k), fe);
+      acc += (T)1 << __umul24(reduce(hash_top(keys[i], X), c.k), fe);
   } else {
 #pragma unroll 4
     for (uint32_t i = lo; i < hi; ++i) {
       const uint32_t ch = __umul24(reduce(hash_top(keys[i], X), c.m), c.magic) >> 20;
-      acc += 1u << __umul24(ch, fe);
+      acc += (T)1 << __umul24(ch, fe);
     }
   }
   return acc;
@@ -508,19 +537,22 @@ __device__ __forceinline__ uint32_t split_count(const uint64_t* keys, const Node
 
 // One chunk of a lower or upper split search (`rounds` rounds from round
 // `first`), keys at `keys`, this wave's three queues at q.
+template <typename T>
 __device__ void run_split_filtered(const uint64_t* keys, const Node& c, uint64_t first,
                                    uint32_t rounds, uint32_t patience, uint64_t* s_best,
                                    uint64_t* q) {
+  using F = SplitFilter<T>;
   const uint32_t lane = lane_id();
   const uint64_t lane_base = first * kWG + (uint64_t)(threadIdx.x >> 6) * 64u;
-  const SplitFilter f = make_split_filter(c);
+  const F f = make_split_filter<T>(c);
   uint64_t* q1 = q;
   uint64_t* q2 = q + kLeafQueue;
   uint64_t* q3 = q + 2 * kLeafQueue;
   uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0, h3 = 0, t3 = 0;  // queue heads and tails
   uint32_t w1 = 0, w2 = 0, w3 = 0;  // rounds the oldest entry of each queue has waited
   auto attempt_of = [&](uint64_t idx) { return (idx >> 6) * kWG + lane_base + (idx & 63u); };
-  auto alive = [&](uint32_t acc) { return (((acc + f.comp) ^ acc ^ f.comp) & f.carries) == 0; };
+  auto alive = [&](T acc) { return (((acc + f.comp) ^ acc ^ f.comp) & f.carries) == 0; };
+  auto pack = [&](uint64_t idx, T acc) { return (idx << F::kIdxShift) | ((uint64_t)acc & F::kAccMask); };
   // stages 2 and 3: the next key range for up to 64 entries of queue qi,
   // survivors to queue qo
   auto middle = [&](uint64_t* qi, uint32_t& hi_, uint64_t* qo, uint32_t& to, uint32_t cnt,
@@ -528,17 +560,18 @@ __device__ void run_split_filtered(const uint64_t* keys, const Node& c, uint64_t
     const bool v = lane < cnt;
     const uint64_t e = v ? qi[(hi_ + lane) & (kLeafQueue - 1)] : 0;
     hi_ += cnt;
-    const uint64_t idx = e >> 32;
-    const uint32_t acc = split_count(keys, c, f.fe, lo, hi, c.start + attempt_of(idx), (uint32_t)e);
-    queue_push(qo, to, v && alive(acc), (idx << 32) | acc);
+    const uint64_t idx = e >> F::kIdxShift;
+    const T acc = split_count<T>(keys, c, f.fe, lo, hi, c.start + attempt_of(idx),
+                                 (T)(e & F::kAccMask));
+    queue_push(qo, to, v && alive(acc), pack(idx, acc));
   };
   // stage 4: the last keys, the word test, exact verification in order
   auto last = [&](uint32_t cnt) -> uint64_t {
     const bool v = lane < cnt;
     const uint64_t e = v ? q3[(h3 + lane) & (kLeafQueue - 1)] : 0;
     h3 += cnt;
-    const uint64_t att = attempt_of(e >> 32);
-    const uint32_t acc = split_count(keys, c, f.fe, f.b3, c.m, c.start + att, (uint32_t)e);
+    const uint64_t att = attempt_of(e >> F::kIdxShift);
+    const T acc = split_count<T>(keys, c, f.fe, f.b3, c.m, c.start + att, (T)(e & F::kAccMask));
     uint64_t cm = __ballot(v && (acc & f.low) == f.target);
     while (cm) {
       const uint32_t L = (uint32_t)__builtin_ctzll(cm);
@@ -554,8 +587,8 @@ __device__ void run_split_filtered(const uint64_t* keys, const Node& c, uint64_t
     const uint64_t cur =
         uni64(__hip_atomic_load(s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
     if (a0 >= cur) break;
-    const uint32_t acc = split_count(keys, c, f.fe, 0, f.b1, c.start + a0 + lane, 0u);
-    queue_push(q1, t1, alive(acc), (((uint64_t)r * 64u + lane) << 32) | acc);
+    const T acc = split_count<T>(keys, c, f.fe, 0, f.b1, c.start + a0 + lane, (T)0);
+    queue_push(q1, t1, alive(acc), pack((uint64_t)r * 64u + lane, acc));
     w1 = t1 != h1 ? w1 + 1 : 0;
     if (t1 - h1 >= 64 || (t1 != h1 && w1 >= patience)) {
       middle(q1, h1, q2, t2, t1 - h1 < 64 ? t1 - h1 : 64, f.b1, f.b2);
@@ -971,7 +1004,7 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
                             const JobDev& J, uint64_t slot, bool own) {
   const uint32_t tid = threadIdx.x;
   constexpr bool leaf = kLeafTask;
-  Node c = make_node(t, J, P.start, P.cap_shift, kMode == kSearchFilter ? 0u : P.rotation_lookup);
+  Node c = make_node(t, J, P.start, P.cap_shift, filter_mode(kMode) ? 0u : P.rotation_lookup);
   stage_keys(t, J, c, s_keys, &sh.na);
   __syncthreads();
   if (leaf) c.na = uni(sh.na);
@@ -982,10 +1015,12 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
   const uint32_t tau = uni((uint32_t)J.tau[c.m]);
   const uint32_t e = tau > P.chunk_shift ? (tau - P.chunk_shift < 8 ? tau - P.chunk_shift : 8) : 0;
   const uint32_t rmax = c.kind == kBinary ? 1u : (1u << e);
-  // the filter kernel's staged split search, where the counters fit and the
-  // queues fit after the node's keys
-  const bool split_filter = kMode == kSearchFilter && !leaf && P.split_filter_tau &&
-                            tau >= P.split_filter_tau && split_filter_fits(c) &&
+  // the filter kernels' staged split search, where the counters fit (32-bit
+  // words, or 64-bit ones in the wide kernel) and the queues fit after the
+  // node's keys
+  using Word = typename std::conditional<kMode == kSearchFilterWide, uint64_t, uint32_t>::type;
+  const bool split_filter = filter_mode(kMode) && !leaf && P.split_filter_tau &&
+                            tau >= P.split_filter_tau && split_filter_fits<Word>(c) &&
                             split_queue_at(c.m) + kSplitQueueWords <= P.stage_cap;
   TaskState* st = P.states + slot;
   uint32_t r = 1;  // thread 0: rounds of this worker's next claim
@@ -1059,10 +1094,10 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
     if (leaf && filtered_leaf(P, tau))
       run_leaf_filtered(c, sh.first, sh.rounds, patience(c, tau), &sh.best);
     else if (split_filter && sh.rounds >= kMinFilterRounds)
-      run_split_filtered(s_keys, c, sh.first, sh.rounds, patience(c, tau), &sh.best,
-                         s_keys + split_queue_at(c.m) + (tid >> 6) * 3 * kLeafQueue);
+      run_split_filtered<Word>(s_keys, c, sh.first, sh.rounds, patience(c, tau), &sh.best,
+                               s_keys + split_queue_at(c.m) + (tid >> 6) * 3 * kLeafQueue);
     else
-      eval_chunk<kMode != kSearchFilter>(s_keys, c, sh.first, sh.rounds, &sh.best);
+      eval_chunk<!filter_mode(kMode)>(s_keys, c, sh.first, sh.rounds, &sh.best);
     __syncthreads();  // the chunk's best is final; every thread has read the decision
     if (tid == 0) {
       const uint64_t v = sh.best;
@@ -1130,7 +1165,7 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
       ct.m = sz;
       ct.depth = (uint16_t)(t.depth + 1);
       ct.job = t.job;
-      run_leaf<kMode == kSearchFilter>(P, sh, s_keys, ct, J, kNoSlot);
+      run_leaf<filter_mode(kMode)>(P, sh, s_keys, ct, J, kNoSlot);
     }
     child_node += uni(J.nodecnt[sz]);
   }
@@ -1155,14 +1190,14 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
       run_claimed<kMode, false>(P, sh, s_keys, t, J, slot, own);
       return;
     }
-    if constexpr (kMode == kSearchFilter) {
+    if constexpr (filter_mode(kMode)) {
       // long leaves (what the filter kernel is chosen for) can be joined
       if (P.join_leaf_tau && uni((uint32_t)J.tau[t.m]) >= P.join_leaf_tau) {
         run_claimed<kMode, true>(P, sh, s_keys, t, J, slot, own);
         return;
       }
     }
-    run_leaf<kMode == kSearchFilter>(P, sh, s_keys, t, J, slot);
+    run_leaf<filter_mode(kMode)>(P, sh, s_keys, t, J, slot);
   }
 }
 
@@ -1443,6 +1478,13 @@ rs_filter_kernel(rs::SearchParams P) {
   rs::search_main<rs::kSearchFilter>(P);
 }
 
+// the same with 64-bit split counters, for leaf sizes 19 to 24 (six waves per
+// SIMD: at seven the wider counters spill vector registers to memory)
+extern "C" __global__ void __launch_bounds__(rs::kWG) __attribute__((amdgpu_waves_per_eu(6)))
+rs_filter_wide_kernel(rs::SearchParams P) {
+  rs::search_main<rs::kSearchFilterWide>(P);
+}
+
 extern "C" __global__ void __launch_bounds__(rs::kWG) rs_bucket_kernel(rs::SearchParams P) {
   rs::search_main<rs::kSearchBucket>(P);
 }
@@ -1457,6 +1499,7 @@ static const void* search_kernel(uint32_t mode) {
   return mode == kSearchBucketWave ? reinterpret_cast<const void*>(rs_wave_bucket_kernel)
          : mode == kSearchBucket   ? reinterpret_cast<const void*>(rs_bucket_kernel)
          : mode == kSearchFilter   ? reinterpret_cast<const void*>(rs_filter_kernel)
+         : mode == kSearchFilterWide ? reinterpret_cast<const void*>(rs_filter_wide_kernel)
                                    : reinterpret_cast<const void*>(rs_search_kernel);
 }
 

@@ -138,6 +138,8 @@ def test_autotuner_runs_and_leaves_defaults():
     best, table = autotune.tune(small_sets=[(5000, 12, 1000)], large_sets=[(20000, 8, 100)],
                                 shifts=(8, 63), help_after=(1, 2), inline_tau=(0, 16),
                                 bucket_leaf=(0, 8), reps=1)
+    assert len(table["bucket_wave"]) == 2 and len(table["rotation_lookup"]) == 2
+    assert best["bucket_wave"] in (0, 1) and best["rotation_lookup"] in (0, 1)
     assert rs().get_schedule() == before
     assert best["chunk_shift_small"] in (8, 63) and best["help_after_large"] in (1, 2)
     assert len(table["small"]) == 4 and len(table["large"]) == 4

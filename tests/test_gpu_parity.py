@@ -9,6 +9,7 @@ configurations follow at full size (the l = 16, b = 2000 build on a sample
 of buckets the oracle can afford).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -305,6 +306,45 @@ def test_leaf_sizes_above_16(n, l, b, rot):
     """The space-efficient leaf sizes of Sec. 6 (l = 18, 20, 24) on sets the
     oracle can afford; l = 24 leaves need values above 2^32."""
     _check_parity(keygen.fingerprints(n, 910 + l + n), l, b, rot)
+
+
+def _large_leaf_sets():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_leaf_sets.txt")
+    rows = []
+    if not os.path.exists(path):  # written by tests/golden/make_large_leaf_sets.py
+        return [pytest.param(0, 0, 0, True, 0, "", marks=pytest.mark.skip(reason=f"{path} missing"))]
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                n, l, b, rot, seed, hexbytes = line.split()
+                rows.append((int(n), int(l), int(b), bool(int(rot)), int(seed), hexbytes))
+    return rows
+
+
+@pytest.mark.parametrize("n,l,b,rot,seed,hexbytes", _large_leaf_sets(),
+                         ids=lambda v: str(v)[:12])
+def test_large_leaf_sets_against_stored_oracle_bytes(n, l, b, rot, seed, hexbytes):
+    """Leaf sizes 19 to 24 on buckets large enough for a fanout-2 root and
+    upper and lower splits (the oracle needs minutes to an hour per set; its
+    bytes are stored by tests/golden/make_large_leaf_sets.py): the default
+    schedule (staged leaf and split searches, 64-bit split counters from
+    l = 19 on), the staged split search forced onto every split, and neither
+    filter all give the oracle's bytes."""
+    want = bytes.fromhex(hexbytes)
+    keys = keygen.fingerprints(n, seed)
+    try:
+        for sched in ({}, {"split_filter_tau": 1, "chunk_shift_small": 0, "chunk_shift_large": 0},
+                      {"split_filter_tau": 0, "leaf_filter_tau": 0}):
+            _case(f"stored oracle bytes n={n} l={l} b={b} rot={rot} {sched}")
+            rs().set_schedule(None)
+            rs().set_schedule(**sched)
+            f = rs().build(keys, l, b, rot)
+            assert f.serialize() == want, sched
+            r = f.query(keys)
+            assert np.array_equal(np.sort(r), np.arange(n, dtype=np.uint64))
+            assert np.array_equal(r, oracle.query(want, keys))
+    finally:
+        rs().set_schedule(None)
 
 
 def test_leaf16_two_buckets():
