@@ -76,13 +76,16 @@ def attempt_evals(st):
 
 WORKLOAD = {"n": 10_000_000, "leaf_size": 16, "bucket_size": 2000, "rotation": True, "seed": 3}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "rs_filter_kernel.l16_b2000_n1e7.pmc.txt")
+# the search kernel and what decides its launch (grid, LDS, mode): the
+# stored counters are used only while all of these are unchanged
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2212_09562_amd", "csrc", f)
-                  for f in ("rs_search.hip", "rs_internal.h")]
+                  for f in ("rs_search.hip", "rs_internal.h", "rs_api.hip", "rs_launch.h")]
 
 
 def kernel_source_hash() -> str:
-    """sha256 of the search kernel's sources with // comments and blank lines
-    removed, so that only code changes invalidate the stored counters."""
+    """sha256 of the search kernel's sources and of the host code that sizes
+    its launches, with // comments and blank lines removed, so that only code
+    changes invalidate the stored counters."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, encoding="utf-8") as fh:
@@ -468,7 +471,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=4.0)
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--per-launch", type=int, default=8)
-    ap.add_argument("--reserve-per-cu", type=int, default=1)
+    ap.add_argument("--reserve-per-cu", type=int, default=0)
     ap.add_argument("--served-only", action="store_true",
                     help="instead: only the served workload (with --budget-gib, --slots, "
                          "--per-launch, --reserve-per-cu)")

@@ -301,7 +301,7 @@ class Server:
     alive here until its result is collected with poll()/wait()."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, max_jobs_per_launch: int = 16,
-                 reserve_per_cu: int = 1):
+                 reserve_per_cu: int = 0):
         cfg = ServerConfig(hbm_budget_bytes, max_slots, max_jobs_per_launch, reserve_per_cu)
         h = ctypes.c_void_p()
         _check(_lib.rs_server_create(ctypes.byref(cfg), ctypes.byref(h)), "rs_server_create")
