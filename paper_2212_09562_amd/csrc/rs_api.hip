@@ -802,13 +802,20 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   // 2. seed search over all nodes of all jobs, one persistent launch
   std::vector<JobDev> jd(nj);  // read by a copy that ends before the wait after the search
   if (total) {
-    const uint32_t lds = bucket_mode ? bucket_lds_bytes(maxm) : words * (uint32_t)sizeof(uint64_t);
+    const uint32_t lds = mode == kSearchBucketWave ? wave_bucket_lds_bytes(maxm)
+                         : bucket_mode             ? bucket_lds_bytes(maxm)
+                                                   : words * (uint32_t)sizeof(uint64_t);
     int per_cu = 0;
     HIPCHECK(search_occupancy(lds, &per_cu, mode));
     if (per_cu < 1) per_cu = 1;
     const uint32_t occ = (uint32_t)per_cu * (uint32_t)d.cus;
-    // one-wave workers: four per four-wave worker the caps allow
-    if (mode == kSearchBucketWave) workers *= 4;
+    // one-wave workers: four per four-wave worker the caps allow, and no more
+    // than there are buckets (a wave without a bucket would only take a slot
+    // on some compute unit that a working wave could have had to itself)
+    if (mode == kSearchBucketWave) {
+      workers *= 4;
+      if ((uint64_t)workers > nbk) workers = (uint32_t)(nbk ? nbk : 1);
+    }
     if (workers > occ) workers = occ;
     HIPCHECK(init_states(A.states, total, s));
     HIPCHECK(fill_u32(A.ready, total, 0, s));

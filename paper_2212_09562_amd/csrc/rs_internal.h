@@ -200,6 +200,15 @@ constexpr uint32_t kWaveBucketSmall = 256;     // one-wave bucket workers whatev
 __host__ __device__ inline uint32_t bucket_lds_bytes(uint32_t cap) {
   return kBucketStackBytes + cap * 18u;
 }
+// One-wave bucket workers add, after that (8-byte aligned), the starting
+// seeds (kMaxDepth words) and one job's subtree node counts (u32) and Rice
+// parameters (u8) for node sizes 0..cap.
+__host__ __device__ inline uint32_t wave_tables_at(uint32_t cap) {
+  return (bucket_lds_bytes(cap) + 7u) & ~7u;
+}
+__host__ __device__ inline uint32_t wave_bucket_lds_bytes(uint32_t cap) {
+  return wave_tables_at(cap) + kMaxDepth * 8u + (cap + 1u) * 5u;
+}
 
 // Search kernels: nodes as tasks; the same with staged (early-exit) leaf and
 // split searches, 32-bit or 64-bit split counters; whole buckets per worker

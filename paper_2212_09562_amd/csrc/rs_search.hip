@@ -130,7 +130,10 @@ struct Node {
   uint64_t cap;  // attempts after which the search is reported as failed
 };
 
-__device__ Node make_node(const Task& t, const JobDev& J, const uint64_t* start,
+// J: the job's shape, leaf method and Rice parameters (a JobDev in global
+// memory, or the one-wave bucket workers' copy in LDS).
+template <typename JobT>
+__device__ Node make_node(const Task& t, const JobT& J, const uint64_t* start,
                           uint32_t cap_shift, uint32_t lookup) {
   Node c;
   Shape s;
@@ -1232,7 +1235,20 @@ __device__ uint64_t wave_eval(const uint64_t* keys, const Node& c) {
   }
 }
 
-__device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t, const JobDev& J) {
+// What make_node reads of a job, for one-wave bucket workers: the shape and
+// leaf method in registers, the Rice parameters in LDS.
+struct WaveJob {
+  uint32_t l, la, ua, rotation;
+  const uint8_t* tau;
+};
+
+// One bucket tree, built by this wave.  The starting seeds and the job's
+// Rice parameters and subtree node counts (for node sizes up to the stage
+// capacity) sit in this wave's LDS after the bucket's arrays (LDS reads
+// instead of dependent global loads on the path of every node).
+__device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t, const JobDev& J,
+                            const uint64_t* s_start, const uint8_t* s_tau,
+                            const uint32_t* s_nodecnt) {
   const uint32_t lane = lane_id();
   const uint32_t cap = P.stage_cap;
   Frame* stack = reinterpret_cast<Frame*>(lds);
@@ -1240,6 +1256,12 @@ __device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t,
   uint64_t* s_tmp = s_keys + cap;
   uint8_t* s_cls = reinterpret_cast<uint8_t*>(s_tmp + cap);
   uint8_t* s_ctmp = s_cls + cap;
+  WaveJob W;
+  W.l = uni(J.l);
+  W.la = uni(J.la);
+  W.ua = uni(J.ua);
+  W.rotation = uni(J.rotation);
+  W.tau = s_tau;
   const Key* src = J.keys[0] + t.key_off;
   for (uint32_t i = lane; i < t.m; i += 64) {
     const Key k = src[i];
@@ -1258,7 +1280,6 @@ __device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t,
   uint32_t sp = 1, done = 0;
   while (sp) {
     __syncthreads();  // one wave: orders the keys and the stack in LDS
-    if (ld_relaxed(&P.ctl->error) != 0) break;
     const Frame f = stack[--sp];
     Task nt;
     nt.key_off = uni(f.off);
@@ -1268,7 +1289,7 @@ __device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t,
     nt.job = t.job;
     uint64_t* keys = s_keys + nt.key_off;
     uint8_t* cls = s_cls + nt.key_off;
-    Node c = make_node(nt, J, P.start, P.cap_shift, P.rotation_lookup);
+    Node c = make_node(nt, W, s_start, P.cap_shift, P.rotation_lookup);
     if (c.kind == kLeaf) {
       // the keys of A (class bit clear) first, in a stable order
       const bool v = lane < c.m;
@@ -1318,7 +1339,7 @@ __device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t,
           if (lane == 0) stack[sp] = g;
           ++sp;
         }
-        cn += uni(J.nodecnt[sz]);
+        cn += uni(s_nodecnt[sz]);
       }
     }
   }
@@ -1331,6 +1352,14 @@ __device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t,
 __device__ void wave_main(const SearchParams& P) {
   extern __shared__ uint64_t lds[];
   const uint32_t lane = lane_id();
+  const uint32_t cap = P.stage_cap;
+  // LDS after the bucket arrays: starting seeds, the current job's Rice
+  // parameters and subtree node counts for sizes 0..cap (wave_bucket_lds_bytes)
+  uint64_t* s_start = lds + wave_tables_at(cap) / sizeof(uint64_t);
+  uint32_t* s_nodecnt = reinterpret_cast<uint32_t*>(s_start + kMaxDepth);
+  uint8_t* s_tau = reinterpret_cast<uint8_t*>(s_nodecnt + cap + 1);
+  for (uint32_t i = lane; i < kMaxDepth; i += 64) s_start[i] = P.start[i];
+  uint32_t job = 0xFFFFFFFFu;  // whose tables are in LDS
   for (;;) {
     uint64_t q = 0;
     if (lane == 0)
@@ -1344,7 +1373,16 @@ __device__ void wave_main(const SearchParams& P) {
     t.m = uni(t.m);
     t.depth = (uint16_t)uni(t.depth);
     t.job = (uint16_t)uni(t.job);
-    wave_bucket(P, lds, t, P.jobs[t.job]);
+    const JobDev& J = P.jobs[t.job];
+    if (t.job != job) {
+      __syncthreads();  // the previous bucket is done with the old tables
+      for (uint32_t i = lane; i <= cap; i += 64) {
+        s_nodecnt[i] = J.nodecnt[i];
+        s_tau[i] = J.tau[i];
+      }
+      job = t.job;
+    }
+    wave_bucket(P, lds, t, J, s_start, s_tau, s_nodecnt);
   }
 }
 
