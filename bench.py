@@ -335,6 +335,13 @@ def _pct(xs, q):
     return xs[min(len(xs) - 1, int(math.ceil(q / 100.0 * len(xs))) - 1)]
 
 
+def _slowest(lat, reqs, k=3):
+    """The k slowest requests: their sizes, arrival times and latencies."""
+    order = sorted(range(len(lat)), key=lambda i: -lat[i])[:k]
+    return [{"n": reqs[i]["n"], "arrival_s": round(reqs[i]["arrival"], 3),
+             "latency_ms": round(lat[i] * 1e3, 2)} for i in order]
+
+
 def _poisson_plain(recsplit, reqs, keys, l, b):
     """Plain rs_build calls, one request at a time in arrival order, each
     started no earlier than its arrival time: latency = done - arrival."""
@@ -426,10 +433,12 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, re
             sweep.append({"rate_per_s": rate,
                           "served": {"latency_ms_p50": _pct(s_lat, 50) * 1e3,
                                      "latency_ms_p99": _pct(s_lat, 99) * 1e3,
-                                     "keys_per_s": total / s_span},
+                                     "keys_per_s": total / s_span,
+                                     "slowest": _slowest(s_lat, fast)},
                           "plain": {"latency_ms_p50": _pct(p_lat, 50) * 1e3,
                                     "latency_ms_p99": _pct(p_lat, 99) * 1e3,
-                                    "keys_per_s": total / p_span}})
+                                    "keys_per_s": total / p_span,
+                                    "slowest": _slowest(p_lat, fast)}})
     sizes = [r["n"] for r in reqs]
     return {"workload": f"{count} requests, Poisson 20/s, sizes log-uniform in [1e4, 1e7] "
                         f"(min {min(sizes)}, max {max(sizes)}), l=12, b=1000, rotation, seed 5",
@@ -444,10 +453,12 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, re
                                "latency_ms_p99": _pct(lat, 99) * 1e3,
                                "admission_wait_ms_p50": _pct(wait, 50) * 1e3,
                                "admission_wait_ms_p99": _pct(wait, 99) * 1e3,
-                               "launches": st_all["launches"] - sat_stats["launches"]},
+                               "launches": st_all["launches"] - sat_stats["launches"],
+                               "slowest": _slowest(lat, reqs)},
             "poisson_plain": {"keys_per_s": total / plain_span,
                               "latency_ms_p50": _pct(plain_lat, 50) * 1e3,
-                              "latency_ms_p99": _pct(plain_lat, 99) * 1e3},
+                              "latency_ms_p99": _pct(plain_lat, 99) * 1e3,
+                              "slowest": _slowest(plain_lat, reqs)},
             "capacity_run": {"launches": sat_stats["launches"],
                              "peak_bytes": sat_stats["peak_bytes"]},
             "load_sweep": sweep}
