@@ -3,8 +3,8 @@ Golomb-Rice records of three buckets of the paper's most space-efficient
 configuration (tab:showcaseOverall: l = 24, b = 2000, rotation fitting,
 n = 5 million random 128-bit keys), on the key set the GPU build of that
 configuration uses (keygen.fingerprints(5_000_000, 55)).  Each bucket costs
-the oracle about half an hour, so the check of the GPU build reads these
-stored results.
+the oracle an hour or more on one core (55 to 89 minutes for these three), so
+the check of the GPU build reads these stored results.
 
 Only the oracle and the seeded key generator are called, one
 single-threaded oracle process per bucket:
@@ -35,9 +35,9 @@ def main():
     res, runs = shards.build_buckets_parallel(keys, L, B, True, BUCKETS, procs=len(BUCKETS))
     with open(OUT, "w") as f:
         f.write("# Oracle results for buckets of keygen.fingerprints(5000000, 55) at l = 24,\n"
-                "# b = 2000, rotation fitting (make_l24_showcase_buckets.py).  Per bucket two\n"
-                "# lines: 'bucket size record_bits' and the record words (hex), then the node\n"
-                "# values in preorder (decimal) on a third line.\n")
+                "# b = 2000, rotation fitting (make_l24_showcase_buckets.py).  Per bucket three\n"
+                "# lines: 'bucket size record_bits', the record words (hex), and the node\n"
+                "# values in preorder (decimal).\n")
         for j in BUCKETS:
             size, vals, words, bits = res[j]
             f.write(f"{j} {size} {bits}\n")

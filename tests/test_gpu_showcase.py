@@ -3,8 +3,8 @@
 128-bit keys).
 
 The build takes about ten minutes on one MI355X, so the test runs only when
-RS_SHOWCASE=1 is set.  Three of its buckets were rebuilt by the oracle (about
-half an hour each; tests/golden/make_l24_showcase_buckets.py stores their
+RS_SHOWCASE=1 is set.  Three of its buckets were rebuilt by the oracle (an
+hour or more each; tests/golden/make_l24_showcase_buckets.py stores their
 node values and Golomb-Rice records); the GPU build must give the same
 values and the same record bits for them, its bucket sizes must match a
 count of the keys, and the ranks of all keys must form a permutation.
