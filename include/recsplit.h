@@ -77,6 +77,13 @@ enum {
  * RS_MAX_BUCKET_KEYS keys), RS_ERR_OOM, RS_ERR_DEVICE, RS_ERR_SEARCH_LIMIT.
  * The result depends only on the key set, l, b and RS_FLAG_ROTATION: it is
  * identical for any key order and any launch configuration.
+ *
+ * With the environment variable RS_PROGRESS set to a number of seconds, a
+ * build (rs_build, rs_build_batch, server launches; not rs_build_noalloc)
+ * prints to stderr at that interval, while its search runs, how many tree
+ * nodes of how many have their final value; searches run by the early-exit
+ * kernel of leaf sizes up to 18 (about a second per million keys) print
+ * nothing.  With RS_DEBUG set, a failed search prints the node that failed.
  */
 int rs_build(const rs_key128 *keys, uint64_t n, uint32_t leaf_size, uint32_t bucket_size,
              uint32_t flags, rs_mphf **out);
@@ -142,11 +149,11 @@ int rs_build_batch(const rs_job *jobs, uint32_t njobs, rs_mphf **outs, int *stat
  * max_slots host threads, each with its own non-blocking HIP stream.
  * Requests queue in arrival order; a free slot takes the oldest waiting
  * requests whose combined working memory fits one free region of the pool
- * (up to max_jobs_per_launch of them; unless at least max_slots requests are
- * waiting, together fewer than 2^20 keys or the oldest alone: a large
- * request is then built alone), builds them together exactly as
- * rs_build_batch does (one persistent search launch), and frees the
- * region.
+ * (up to max_jobs_per_launch of them; a request of 2^20 keys or more is
+ * built alone, smaller ones together while their keys stay below 2^20 or,
+ * when at least max_slots requests are waiting, until they reach it),
+ * builds them together exactly as rs_build_batch does (one persistent
+ * search launch), and frees the region.
  * Slots run concurrently, so newly arrived requests are admitted while
  * earlier ones are still on the device and their kernels overlap.  A request
  * whose own working memory exceeds the budget is refused at submission
@@ -170,8 +177,8 @@ typedef struct {
   uint32_t max_jobs_per_launch; /* requests per search launch, >= 1 */
   uint32_t reserve_per_cu;      /* search workgroups per compute unit that launches
                                    leave free (0: none); large launches (2^20 keys or
-                                   more) then run one at a time unless max_slots
-                                   requests are waiting, and a small launch made while
+                                   more) run one at a time, in admission order, unless
+                                   max_slots requests are waiting, and a small launch made while
                                    one runs uses only the reserve, so small requests
                                    do not wait behind large ones */
 } rs_server_config;

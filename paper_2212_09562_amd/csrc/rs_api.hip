@@ -12,7 +12,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "rs_host.h"
@@ -333,6 +335,8 @@ void context_destroy(Context& c) {
   }
   if (c.upstream) (void)hipEventDestroy(c.upstream);
   c.upstream = nullptr;
+  if (c.progress) (void)hipHostFree(c.progress);
+  c.progress = c.progress_dev = nullptr;
   if (c.s) (void)hipStreamDestroy(c.s);
   c.s = nullptr;
 }
@@ -643,6 +647,34 @@ void encode_words(Context& c, const Arrays& A, std::vector<JobPlan>& jobs,
 
 namespace rs {
 
+// Seconds between progress lines during a search (RS_PROGRESS; 0: none).
+double progress_every() {
+  const char* e = getenv("RS_PROGRESS");
+  const double v = e ? atof(e) : 0.0;
+  return v > 0.0 ? v : 0.0;
+}
+
+// Wait for the search to end, printing the finished node count to stderr
+// every `every` seconds (the search kernels store it into the context's
+// host-pinned word every 2^kProgressShift nodes).
+void wait_with_progress(Context& c, uint64_t total, double every) {
+  using clock = std::chrono::steady_clock;
+  const clock::time_point t0 = clock::now();
+  double next = every;
+  uint64_t seen = 0;
+  while (hipEventQuery(c.ev[4]) == hipErrorNotReady) {
+    std::this_thread::sleep_for(std::chrono::milliseconds(20));
+    const double el = std::chrono::duration<double>(clock::now() - t0).count();
+    if (el < next) continue;
+    const uint64_t f = __atomic_load_n(c.progress, __ATOMIC_RELAXED);
+    if (f > seen) seen = f;
+    fprintf(stderr, "[rs progress] search: %llu of %llu nodes final after %.0f s\n",
+            (unsigned long long)seen, (unsigned long long)total, el);
+    fflush(stderr);
+    next += every;
+  }
+}
+
 int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t region_bytes,
                uint32_t workers_cap) {
   Device& d = *c.dev;
@@ -801,6 +833,9 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
 
   // 2. seed search over all nodes of all jobs, one persistent launch
   std::vector<JobDev> jd(nj);  // read by a copy that ends before the wait after the search
+  // progress lines (the filter kernel, whose searches end within seconds,
+  // does not report)
+  double progress = mode == kSearchFilter ? 0.0 : progress_every();
   if (total) {
     const uint32_t lds = mode == kSearchBucketWave ? wave_bucket_lds_bytes(maxm)
                          : bucket_mode             ? bucket_lds_bytes(maxm)
@@ -841,6 +876,20 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     // (jd and total stay alive until the wait after the search)
     HIPCHECK(h2d_async(c, A.jobs, jd.data(), nj * sizeof(JobDev)));
     HIPCHECK(h2d_async(c, &A.ctl->total, &total, sizeof(uint64_t)));
+    if (progress && &c != &d.noalloc) {
+      if (!c.progress) {
+        void* h = nullptr;
+        HIPCHECK(hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent));
+        c.progress = static_cast<uint64_t*>(h);
+        void* dp = nullptr;
+        HIPCHECK(hipHostGetDevicePointer(&dp, h, 0));
+        c.progress_dev = static_cast<uint64_t*>(dp);
+      }
+      __atomic_store_n(c.progress, 0ull, __ATOMIC_RELAXED);
+      HIPCHECK(h2d_async(c, &A.ctl->progress, &c.progress_dev, sizeof(uint64_t*)));
+    } else {
+      progress = 0.0;
+    }
     for (uint32_t i = 0; i < nj; ++i) {
       JobPlan& j = jobs[i];
       if (j.status || !j.total) continue;
@@ -881,6 +930,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     HIPCHECK(hipEventRecord(c.ev[3], s));
   }
   HIPCHECK(hipEventRecord(c.ev[4], s));
+  if (progress > 0.0) wait_with_progress(c, total, progress);
   // useful work of every job, counted from its node values (harmless after a
   // stopped search, whose results are dropped), read back with the control
   // block in one wait

@@ -38,6 +38,8 @@ struct Context {
   Buffer qkeys, qout, sc_counts, sc_prefix, sc_tmp;
   hipEvent_t ev[6] = {};
   hipEvent_t upstream = nullptr;  // orders the context after the legacy default stream
+  uint64_t* progress = nullptr;   // host-pinned finished count of the running search
+  uint64_t* progress_dev = nullptr;  // its device address
   std::mutex mu;
 };
 

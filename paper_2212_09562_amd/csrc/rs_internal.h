@@ -181,9 +181,13 @@ struct Control {
   // the node that raised the first error (diagnostics)
   uint64_t dbg_key_off, dbg_node, dbg_slot, dbg_np, dbg_best, dbg_chunk;
   uint32_t dbg_m, dbg_depth;
-  uint64_t pad_end[23];
+  // host-pinned word that receives the finished count at every
+  // 2^kProgressShift-th node (null: progress not reported)
+  uint64_t* progress;
+  uint64_t pad_end[22];
 };
 static_assert(sizeof(Control) % 256 == 0, "Control lines");
+constexpr uint32_t kProgressShift = 10;
 
 // Rotation fitting with lookup tables (Sec. 4): for every leaf size m up to
 // kRotLookupMaxM and every m-bit word x, entry (1 << m) + x holds in bits

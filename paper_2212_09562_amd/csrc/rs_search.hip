@@ -662,6 +662,27 @@ __device__ __forceinline__ bool queued_child(const SearchParams& P, const JobDev
   return sz >= 2 && (sz > l || (uint32_t)J.tau[sz] >= P.inline_leaf_tau);
 }
 
+// Count finished nodes.  Kernels that report progress (all but the filter
+// kernel, whose searches end within seconds) also store the running count
+// into the host's word at every 2^kProgressShift-th node when one is given (a
+// plain store at system scope: the host keeps the largest value it has seen).
+constexpr bool reports_progress(uint32_t mode) { return mode != kSearchFilter; }
+
+template <bool kReport>
+__device__ __forceinline__ void note_finished(const SearchParams& P, uint64_t inc) {
+  if constexpr (kReport) {
+    const uint64_t was =
+        __hip_atomic_fetch_add(&P.ctl->finished, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (((was + inc) >> kProgressShift) != (was >> kProgressShift)) {
+      uint64_t* host = P.ctl->progress;
+      if (host) __hip_atomic_store(host, was + inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  } else {
+    __hip_atomic_fetch_add(&P.ctl->finished, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <bool kReport>
 __device__ void finalize_split(const SearchParams& P, const Task& t, const JobDev& J,
                                const Node& c, uint64_t s) {
   const uint32_t lane = lane_id();
@@ -727,17 +748,18 @@ __device__ void finalize_split(const SearchParams& P, const Task& t, const JobDe
   if (lane == 0) {
     if (queued)
       for (uint32_t i = 0; i < nkids; ++i) st_relaxed(&P.ready[base + i], 1u);
-    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    note_finished<kReport>(P, 1ull);
   }
 }
 
 // A leaf's value is read only after the launch: no ordering needed.
+template <bool kReport>
 __device__ void finalize_leaf(const SearchParams& P, const Task& t, const JobDev& J,
                               const Node& c, uint64_t v) {
   if (threadIdx.x == 0) {
     J.vals[t.node] = v;
     J.msz[t.node] = c.m;
-    __hip_atomic_fetch_add(&P.ctl->finished, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    note_finished<kReport>(P, 1ull);
   }
 }
 
@@ -806,7 +828,7 @@ __device__ __forceinline__ uint32_t patience(const Node& c, uint32_t tau) {
 // of the filter kernel, leaves whose Rice parameter reaches join_leaf_tau go
 // through the claimed chunks of run_claimed instead, so that idle workers can
 // join them.
-template <bool kFilter>
+template <bool kFilter, bool kReport>
 __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, const Task& t,
                          const JobDev& J, uint64_t slot) {
   const uint32_t tid = threadIdx.x;
@@ -830,7 +852,7 @@ __device__ void run_leaf(const SearchParams& P, Shared& sh, uint64_t* s_keys, co
     if (tid == 0 && set_error(P.ctl, (uint32_t)(-RS_ERR_SEARCH_LIMIT)))
       record_failure(P.ctl, t, slot, P.states + (slot < P.ctl->total ? slot : 0), 0);
   } else {
-    finalize_leaf(P, t, J, c, v);
+    finalize_leaf<kReport>(P, t, J, c, v);
   }
   __syncthreads();
 }
@@ -990,9 +1012,7 @@ __device__ void run_bucket(const SearchParams& P, Shared& sh, uint64_t* lds, con
       }
     }
   }
-  if (tid == 0 && done)
-    __hip_atomic_fetch_add(&P.ctl->finished, (uint64_t)done, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0 && done) note_finished<true>(P, (uint64_t)done);
   __syncthreads();
 }
 
@@ -1150,11 +1170,11 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
   __syncthreads();
   const uint64_t v = sh.fin_value;
   if constexpr (leaf) {
-    finalize_leaf(P, t, J, c, v);
+    finalize_leaf<reports_progress(kMode)>(P, t, J, c, v);
     __syncthreads();
     return;
   }
-  if (tid < 64) finalize_split(P, t, J, c, v);
+  if (tid < 64) finalize_split<reports_progress(kMode)>(P, t, J, c, v);
   __syncthreads();
   // the leaf children kept out of the queue, searched here in order
   const uint32_t l = uni(J.l);
@@ -1168,7 +1188,7 @@ __device__ void run_claimed(const SearchParams& P, Shared& sh, uint64_t* s_keys,
       ct.m = sz;
       ct.depth = (uint16_t)(t.depth + 1);
       ct.job = t.job;
-      run_leaf<filter_mode(kMode)>(P, sh, s_keys, ct, J, kNoSlot);
+      run_leaf<filter_mode(kMode), reports_progress(kMode)>(P, sh, s_keys, ct, J, kNoSlot);
     }
     child_node += uni(J.nodecnt[sz]);
   }
@@ -1200,7 +1220,7 @@ __device__ void run_task(const SearchParams& P, Shared& sh, uint64_t* s_keys, ui
         return;
       }
     }
-    run_leaf<filter_mode(kMode)>(P, sh, s_keys, t, J, slot);
+    run_leaf<filter_mode(kMode), reports_progress(kMode)>(P, sh, s_keys, t, J, slot);
   }
 }
 
@@ -1343,9 +1363,7 @@ __device__ void wave_bucket(const SearchParams& P, uint64_t* lds, const Task& t,
       }
     }
   }
-  if (lane == 0 && done)
-    __hip_atomic_fetch_add(&P.ctl->finished, (uint64_t)done, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0 && done) note_finished<true>(P, (uint64_t)done);
   __syncthreads();
 }
 

@@ -16,6 +16,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -104,6 +105,8 @@ struct rs_server {
   uint32_t reserve_workers = 0;  // the reserve (reserve_per_cu workers on every CU)
   uint32_t large_running = 0;  // large launches in progress
   std::condition_variable cv_large;
+  uint64_t large_seq = 0;            // admission number of the next large launch
+  std::set<uint64_t> large_pending;  // large launches admitted, not yet started
   rs_server_stats st{};
   size_t in_use = 0;
   size_t usable = 0;  // pool bytes in whole regions
@@ -127,18 +130,19 @@ void slot_loop(rs_server* S, uint32_t slot) {
     std::vector<uint64_t> tickets;
     std::vector<JobPlan> plan;
     size_t off = 0, bytes = 0;
-    bool backlog = false;
+    bool backlog = false, large = false;
+    uint64_t seq = 0;
     {
       std::unique_lock<std::mutex> lock(S->mu);
       for (;;) {
         if (S->stopping) return;
         if (!S->waiting.empty()) {
           // The oldest requests that fit one free region, in arrival order.
-          // With a short queue (latency first) a large request is built
-          // alone and small ones are batched only while their keys stay below
-          // the large-launch size, so no request waits for the end of a
-          // larger one's search; with a backlog (at least one request per
-          // slot waiting: throughput first) any requests are batched.
+          // A large request is always built alone, so no smaller request
+          // waits for the end of its search.  With a short queue (latency
+          // first) small ones are batched only while their keys stay below
+          // the large-launch size; with a backlog (at least one request per
+          // slot waiting: throughput first) up to the per-launch limit.
           backlog = S->waiting.size() >= S->ctx.size();
           const size_t room = S->regions.largest();
           std::vector<JobPlan> trial;
@@ -147,7 +151,10 @@ void slot_loop(rs_server* S, uint32_t slot) {
           for (uint64_t t : S->waiting) {
             if (trial.size() >= S->cfg.max_jobs_per_launch) break;
             const Request& r = S->reqs[t];
-            if (!backlog && !trial.empty() && batch_keys + r.job.n >= kLargeLaunchKeys) break;
+            if (!trial.empty() &&
+                (r.job.n >= kLargeLaunchKeys || batch_keys >= kLargeLaunchKeys ||
+                 (!backlog && batch_keys + r.job.n >= kLargeLaunchKeys)))
+              break;
             batch_keys += r.job.n;
             JobPlan p;
             p.keys = reinterpret_cast<const Key*>(r.job.keys);
@@ -179,6 +186,13 @@ void slot_loop(rs_server* S, uint32_t slot) {
             S->in_use += bytes;
             if (S->in_use > S->st.peak_bytes) S->st.peak_bytes = S->in_use;
             S->st.launches += 1;
+            uint64_t keys = 0;
+            for (const JobPlan& p : plan) keys += p.n;
+            large = keys >= kLargeLaunchKeys;
+            if (large) {
+              seq = S->large_seq++;
+              S->large_pending.insert(seq);
+            }
             break;
           }
         }
@@ -187,23 +201,26 @@ void slot_loop(rs_server* S, uint32_t slot) {
     }
     // Device sharing.  A large launch holds the device for a long time and
     // leaves the reserve free; without a backlog large launches run one at a
-    // time (with one, they overlap and fill each other's tails).  A small
-    // launch that starts while a large one runs is sized to the reserve, so
-    // it finishes without waiting for the large one; otherwise a small launch
-    // takes the whole device (it ends soon).
-    uint64_t keys = 0;
-    for (const JobPlan& p : plan) keys += p.n;
-    const bool large = keys >= kLargeLaunchKeys;
+    // time, in the order they were admitted (with one, they overlap and fill
+    // each other's tails).  A small launch that starts while a large one runs
+    // is sized to the reserve, so it finishes without waiting for the large
+    // one; otherwise a small launch takes the whole device (it ends soon).
     uint32_t cap = 0;
-    {
-      std::unique_lock<std::mutex> lock(S->mu);
-      if (large) {
-        if (!backlog) S->cv_large.wait(lock, [&] { return !S->large_running || S->stopping; });
+    if (large) {
+      {
+        std::unique_lock<std::mutex> lock(S->mu);
+        if (!backlog)
+          S->cv_large.wait(lock, [&] {
+            return S->stopping || (!S->large_running && *S->large_pending.begin() == seq);
+          });
+        S->large_pending.erase(seq);
         S->large_running += 1;
         cap = S->workers_cap;
-      } else if (S->large_running && S->reserve_workers) {
-        cap = S->reserve_workers;
       }
+      S->cv_large.notify_all();  // the next large launch in order may now wait its turn
+    } else {
+      std::lock_guard<std::mutex> lock(S->mu);
+      if (S->large_running && S->reserve_workers) cap = S->reserve_workers;
     }
     int rc = build_jobs(c, plan, S->pool + off, bytes, cap);
     if (rc) {

@@ -295,6 +295,29 @@ def test_stall_guard_stops_a_launch_and_the_library_recovers():
     _check_parity(keys, 12, 1000, True, "after a stopped launch")
 
 
+def test_progress_lines(capfd):
+    """RS_PROGRESS=<seconds>: while a search runs, the library prints the
+    number of finished nodes to stderr at that interval.  The counts never
+    decrease and never exceed the node total, and the structure is the same
+    as without the lines."""
+    keys = keygen.fingerprints_torch(1_000_000, 77, "cuda")
+    _case("progress lines, l=20 b=100 n=1e6")
+    ref = rs().build(keys, 20, 100, True).serialize()
+    os.environ["RS_PROGRESS"] = "0.1"
+    try:
+        data = rs().build(keys, 20, 100, True).serialize()
+    finally:
+        del os.environ["RS_PROGRESS"]
+    err = capfd.readouterr().err
+    lines = [ln.split() for ln in err.splitlines() if ln.startswith("[rs progress]")]
+    assert len(lines) >= 2, err
+    done = [int(w[3]) for w in lines]
+    total = {int(w[5]) for w in lines}
+    assert len(total) == 1
+    assert done == sorted(done) and done[-1] <= total.pop()
+    assert data == ref
+
+
 def test_largest_buckets():
     _case("b=4096, n=12000, l=8")
     _check_parity(keygen.fingerprints(12000, 15), 8, 4096, True)

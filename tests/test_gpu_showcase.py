@@ -49,6 +49,9 @@ def test_l24_b2000_five_million_keys():
     torch.cuda.synchronize()
     print(f"[case] l={l} b={b} n={n}, buckets {sorted(want)} against the oracle", flush=True)
     recsplit.build(dev[:2000], l, b, True).free()  # the leaf size's tables
+    # the search's own progress (finished nodes) on stderr every 30 s; run
+    # with -s to see it
+    os.environ.setdefault("RS_PROGRESS", "30")
     t0 = time.perf_counter()
     f = recsplit.build(dev, l, b, True, keep_values=True)
     secs = time.perf_counter() - t0
