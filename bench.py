@@ -240,6 +240,7 @@ def run_small_config(recsplit, keygen, torch, n, seed, rotation, rates, reps=7):
     keys = keygen.fingerprints(n, seed)
     dev = torch.from_numpy(keys.view(np.int64)).cuda()
     torch.cuda.synchronize()
+    ranks = torch.empty(n, dtype=torch.int64, device="cuda")
     recsplit.build(dev, l, b, rotation).free()
     times, stats = [], []
     f = None
@@ -248,9 +249,11 @@ def run_small_config(recsplit, keygen, torch, n, seed, rotation, rates, reps=7):
             f.free()
         t0 = time.perf_counter()
         f = recsplit.build(dev, l, b, rotation)
+        f.query(dev, ranks)  # the ranks of all keys (synchronous)
         times.append(time.perf_counter() - t0)
         stats.append(f.stats())
     gpu_bytes = f.serialize()
+    gpu_ranks = ranks.cpu().numpy().view(np.uint64)
     f.free()
     med = sorted(times)[len(times) // 2]
     st = stats[-1]
@@ -259,17 +262,24 @@ def run_small_config(recsplit, keygen, torch, n, seed, rotation, rates, reps=7):
     t0 = time.perf_counter()
     want, _ = oracle.build(keys, l, b, rotation)
     t_oracle = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    want_ranks = oracle.query(want, keys)
+    t_oracle_q = time.perf_counter() - t0
     out = {"n": n, "leaf_size": l, "bucket_size": b,
            "leaf_method": "rotation" if rotation else "brute",
            "keys_per_s": n / med, "ms_per_build_median": med * 1e3,
+           "step": "build, then the ranks of all keys",
            "stage_ms": {k: sorted(x[k] for x in stats)[len(stats) // 2]
                         for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},
            "bits_per_key": st["bytes"] * 8 / n,
            "search": _search_roofline(evals, ms_search, rates),
            "identical_to_oracle": gpu_bytes == want,
-           "cpu_baseline": {"value": n / t_oracle, "unit": "keys/s", "cores": 1,
-                            "kind": "oracle", "seconds": t_oracle,
-                            "sample": f"the whole {n}-key set, one single-threaded oracle call"}}
+           "ranks_identical_to_oracle": bool(np.array_equal(gpu_ranks, want_ranks)),
+           "cpu_baseline": {"value": n / (t_oracle + t_oracle_q), "unit": "keys/s", "cores": 1,
+                            "kind": "oracle", "seconds": t_oracle + t_oracle_q,
+                            "seconds_build": t_oracle, "seconds_ranks": t_oracle_q,
+                            "sample": f"the whole {n}-key set, one single-threaded oracle "
+                                      "build and query"}}
     return out
 
 
@@ -550,17 +560,23 @@ def main():
     torch.cuda.synchronize()
     stats, step_s = [], []
     f = None
+    ranks = torch.empty(n, dtype=torch.int64, device="cuda")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         if f is not None:
             f.free()
         a = time.perf_counter()
+        # one step: the construction, then the ranks of all keys (synchronous)
         f = recsplit.build(dev, l, b, rot)
+        f.query(dev, ranks)
         step_s.append(time.perf_counter() - a)
         stats.append(f.stats())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     secs = t1 - t0
+    ranks_ok = bool(torch.equal(torch.sort(ranks)[0],
+                                torch.arange(n, device=ranks.device, dtype=ranks.dtype)))
+    del ranks
     query = run_query(f, dev, torch)
     gpu_bytes = f.serialize()
     f.free()
@@ -614,6 +630,8 @@ def main():
                      "calibrated_hash_loop_evals_per_s": rates["hash_evals"],
                      "sustained_hash_loop_evals_per_s": rates["hash_evals_sustained"]},
         "bits_per_key": st["bytes"] * 8 / n,
+        "step": "construction, then the ranks of all keys (rs_query)",
+        "ranks_permutation": ranks_ok,
         "query": query,
         "stage_ms": {k: sum(s[k] for s in stats) / len(stats)
                      for k in ("ms_sort", "ms_search", "ms_encode", "ms_total")},

@@ -255,6 +255,7 @@ struct rs_mphf {
   bool dev_ready = false;
   uint64_t* d_words = nullptr;
   uint64_t* d_samples = nullptr;  // samples of C, then of P
+  uint64_t* d_offsets = nullptr;  // (C_j, P_j) decoded, when no larger than the words
   uint64_t ns_c = 0, ns_p = 0;
   rs_stats stats{};
   std::vector<uint64_t> keep_vals, keep_base;
@@ -364,6 +365,7 @@ void mphf_release(rs_mphf* f) {
   if (!f) return;
   if (f->d_words) (void)hipFree(f->d_words);
   if (f->d_samples) (void)hipFree(f->d_samples);
+  if (f->d_offsets) (void)hipFree(f->d_offsets);
   delete f;
 }
 
@@ -406,14 +408,29 @@ namespace {
 // Device copy of the serialised words plus select samples of both upper
 // vectors; checks that each upper vector holds exactly N ones.  Caller holds
 // f->dev_mu.
+// The device views of the two Elias-Fano sequences of an attached structure.
+void ef_views(const rs_mphf* f, EFView* C, EFView* P) {
+  C->lower = f->d_words + f->efc.at + kEfHeaderWords;
+  C->upper = C->lower + f->efc.lw;
+  C->samples = f->d_samples;
+  C->N = f->efc.N;
+  C->L = (uint32_t)f->efc.L;
+  P->lower = f->d_words + f->efp.at + kEfHeaderWords;
+  P->upper = P->lower + f->efp.lw;
+  P->samples = f->d_samples + f->ns_c;
+  P->N = f->efp.N;
+  P->L = (uint32_t)f->efp.L;
+}
+
 int attach_device(Context& c, rs_mphf* f) {
   const uint64_t nw = f->words.size();
   f->d_words = nullptr;
   f->d_samples = nullptr;
+  f->d_offsets = nullptr;
   HIPCHECK(hipMalloc(&f->d_words, nw * sizeof(uint64_t)));
   HIPCHECK(h2d(c, f->d_words, f->words.data(), nw * sizeof(uint64_t)));
-  f->ns_c = (f->efc.N + 255) / 256;
-  f->ns_p = (f->efp.N + 255) / 256;
+  f->ns_c = (f->efc.N + (1u << kSampleShift) - 1) >> kSampleShift;
+  f->ns_p = (f->efp.N + (1u << kSampleShift) - 1) >> kSampleShift;
   HIPCHECK(hipMalloc(&f->d_samples, (f->ns_c + f->ns_p + 2) * sizeof(uint64_t)));
   const EFLayout* efs[2] = {&f->efc, &f->efp};
   uint64_t* samp[2] = {f->d_samples, f->d_samples + f->ns_c};
@@ -430,6 +447,16 @@ int attach_device(Context& c, rs_mphf* f) {
     uint64_t ones = 0;
     if (e.uw) HIPCHECK(d2h(c, &ones, prefix + e.uw, sizeof ones));
     if (ones != e.N) return RS_ERR_CORRUPT;
+  }
+  // Both sequences decoded into one array when it is no larger than the
+  // structure (or 1 MiB): a query then reads C_j, P_j and C_{j+1} with two
+  // loads instead of three selects.
+  const uint64_t N = f->efc.N;
+  if (N == f->efp.N && N * 16 <= (nw * 8 > (1u << 20) ? nw * 8 : (1u << 20))) {
+    HIPCHECK(hipMalloc(&f->d_offsets, N * 16));
+    EFView C, P;
+    ef_views(f, &C, &P);
+    HIPCHECK(decode_offsets(C, P, N, f->d_offsets, c.s));
   }
   f->device = c.dev->id;
   f->dev_ready = true;
@@ -1149,7 +1176,8 @@ int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out,
       if (rc) {
         if (g->d_words) (void)hipFree(g->d_words);
         if (g->d_samples) (void)hipFree(g->d_samples);
-        g->d_words = g->d_samples = nullptr;
+        if (g->d_offsets) (void)hipFree(g->d_offsets);
+        g->d_words = g->d_samples = g->d_offsets = nullptr;
         return rc;
       }
     } else if (g->device != d.id) {
@@ -1169,16 +1197,8 @@ int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out,
     od = static_cast<uint64_t*>(c->qout.p);
   }
   QueryParams q;
-  q.C.lower = f->d_words + f->efc.at + kEfHeaderWords;
-  q.C.upper = q.C.lower + f->efc.lw;
-  q.C.samples = f->d_samples;
-  q.C.N = f->efc.N;
-  q.C.L = (uint32_t)f->efc.L;
-  q.P.lower = f->d_words + f->efp.at + kEfHeaderWords;
-  q.P.upper = q.P.lower + f->efp.lw;
-  q.P.samples = f->d_samples + f->ns_c;
-  q.P.N = f->efp.N;
-  q.P.L = (uint32_t)f->efp.L;
+  ef_views(f, &q.C, &q.P);
+  q.offsets = f->d_offsets;
   q.gr = f->d_words + f->gr_at + 2;
   q.gr_bits = f->gr_bits;
   q.nb = f->nb;
@@ -1188,6 +1208,10 @@ int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out,
   q.fixedbits = T->fixedbits;
   q.tau = T->tau;
   q.start = d.start;
+  auto magic = [](uint32_t dv) { return (uint32_t)(((1ull << 32) + dv - 1) / dv); };
+  q.magic_l = magic(q.shape.l);
+  q.magic_la = magic(q.shape.la);
+  q.magic_ua = magic(q.shape.ua);
   HIPCHECK(launch_query(q, kd, n, od, c->s));
   if (!on_dev) HIPCHECK(d2h(*c, out, od, n * sizeof(uint64_t)));
   else HIPCHECK(hipStreamSynchronize(c->s));

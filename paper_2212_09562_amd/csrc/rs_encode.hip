@@ -97,16 +97,26 @@ __global__ void k_ef(const uint64_t* x, uint64_t N, uint32_t L, uint64_t* lower,
 }
 
 // Position of the k-th (0-based) set bit of x; x has more than k set bits.
+// A binary search over the popcounts of halves, quarters, ...: the same
+// instructions for every lane.
 __device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t k) {
-  uint32_t base = 0;
-  const uint32_t c = (uint32_t)__popc((uint32_t)x);
+  uint32_t pos = 0;
+  uint32_t c = (uint32_t)__popc((uint32_t)x);
   if (k >= c) {
     k -= c;
-    x >>= 32;
-    base = 32;
+    pos = 32;
   }
-  for (uint32_t i = 0; i < k; ++i) x &= x - 1;
-  return base + (uint32_t)__builtin_ctzll(x);
+  uint32_t w = (uint32_t)(x >> pos);
+#pragma unroll
+  for (uint32_t half = 16; half >= 1; half >>= 1) {
+    c = (uint32_t)__popc(w & ((1u << half) - 1u));
+    if (k >= c) {
+      k -= c;
+      pos += half;
+      w >>= half;
+    }
+  }
+  return pos;
 }
 
 __global__ void k_popc_words(const uint64_t* w, uint64_t n, uint64_t* out) {
@@ -120,15 +130,17 @@ __global__ void k_samples(const uint64_t* w, uint64_t n, const uint64_t* prefix,
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t r0 = prefix[i], r1 = prefix[i + 1];
-    for (uint64_t k = (r0 + 255) >> 8; (k << 8) < r1 && k < nsamples; ++k)
-      samples[k] = i * 64 + select_in_word(w[i], (uint32_t)((k << 8) - r0));
+    constexpr uint64_t step = 1ull << kSampleShift;
+    for (uint64_t k = (r0 + step - 1) >> kSampleShift; (k << kSampleShift) < r1 && k < nsamples;
+         ++k)
+      samples[k] = i * 64 + select_in_word(w[i], (uint32_t)((k << kSampleShift) - r0));
   }
 }
 
 // Position of the i-th one of an Elias-Fano upper vector.
 __device__ uint64_t ef_select(const EFView& e, uint64_t i) {
-  uint64_t p = e.samples[i >> 8];
-  uint32_t need = (uint32_t)(i & 255);
+  uint64_t p = e.samples[i >> kSampleShift];
+  uint32_t need = (uint32_t)(i & ((1u << kSampleShift) - 1u));
   uint64_t wi = p >> 6;
   uint64_t word = e.upper[wi] & (~0ull << (p & 63));
   for (;;) {
@@ -151,6 +163,29 @@ __device__ __forceinline__ uint64_t read_bits(const uint64_t* w, uint64_t pos, u
 __device__ uint64_t ef_get(const EFView& e, uint64_t i) {
   const uint64_t hi = ef_select(e, i) - i;
   return (hi << e.L) | read_bits(e.lower, i * e.L, e.L);
+}
+
+// Elements i and i + 1 (i + 1 < N): the one of element i + 1 is the next one
+// after that of element i.
+__device__ void ef_get2(const EFView& e, uint64_t i, uint64_t* a, uint64_t* b) {
+  const uint64_t p = ef_select(e, i);
+  uint64_t wi = (p + 1) >> 6;
+  uint64_t word = e.upper[wi] & (~0ull << ((p + 1) & 63));
+  while (!word) word = e.upper[++wi];
+  const uint64_t q = wi * 64 + (uint64_t)__builtin_ctzll(word);
+  *a = ((p - i) << e.L) | read_bits(e.lower, i * e.L, e.L);
+  *b = ((q - i - 1) << e.L) | read_bits(e.lower, (i + 1) * e.L, e.L);
+}
+
+// v mod m for a leaf size m: through double precision while v < 2^53 (one
+// correction step makes it exact), else the integer division.
+__device__ __forceinline__ uint32_t mod_leaf(uint64_t v, uint32_t m) {
+  if (v >> 53) return (uint32_t)(v % m);
+  uint64_t q = (uint64_t)((double)v * (1.0 / (double)m));
+  int64_t r = (int64_t)(v - q * m);
+  if (r < 0) r += m;
+  if (r >= (int64_t)m) r -= m;
+  return (uint32_t)r;
 }
 
 // Count the zeros before the next one at or after *pos; advance past the one.
@@ -195,12 +230,18 @@ __global__ void __launch_bounds__(256) k_query(QueryParams Q, const Key* keys, u
   if (idx >= n) return;
   const Key key = keys[idx];
   const uint64_t j = __umul64hi(key.w0, Q.nb);
-  const uint64_t cj = ef_get(Q.C, j);
-  const uint64_t cj1 = ef_get(Q.C, j + 1);
+  uint64_t cj, cj1, pj;
+  if (Q.offsets) {
+    cj = Q.offsets[2 * j];
+    pj = Q.offsets[2 * j + 1];
+    cj1 = Q.offsets[2 * j + 2];
+  } else {
+    ef_get2(Q.C, j, &cj, &cj1);
+    pj = ef_get(Q.P, j);
+  }
   uint64_t m64 = cj1 - cj;
   if (m64 > kMaxBucketKeys) m64 = 0;
   uint32_t m = (uint32_t)m64;
-  const uint64_t pj = ef_get(Q.P, j);
   const uint64_t end = Q.gr_bits;
   uint64_t fp = pj, up = pj + Q.fixedbits[m];
   uint64_t offset = 0, pos = 0;
@@ -216,29 +257,47 @@ __global__ void __launch_bounds__(256) k_query(QueryParams Q, const Key* keys, u
     const uint64_t start = Q.start[depth];
     if (kd == kLeaf) {
       if (Q.rotation) {
-        const uint64_t r = v % m;
+        const uint32_t r = mod_leaf(v, m);
         pos = reduce(hash_top(key.w1, start + (v - r)), m);
-        if (key.w0 & 1u) pos = (pos + r) % m;
+        if (key.w0 & 1u) {
+          pos += r;
+          if (pos >= m) pos -= m;
+        }
       } else {
         pos = reduce(hash_top(key.w1, start + v), m);
       }
       break;
     }
     const uint32_t p = reduce(hash_top(key.w1, start + v), m);
-    const Parts pr = parts_of(Q.shape, m);
-    const uint32_t c = kd == kBinary ? (p >= pr.unit ? 1u : 0u) : p / pr.unit;
-    uint64_t skip_nodes = 0;
-    for (uint32_t k = 0; k < c; ++k) {
-      const uint32_t sz = part_size(pr, k);
-      offset += sz;
-      fp += Q.fixedbits[sz];
-      skip_nodes += Q.nodecnt[sz];
+    // the children (parts_of, with the divisions by multiply-high): every
+    // child before the last has size `unit`
+    uint32_t unit, k, c;
+    if (kd == kBinary) {
+      const uint32_t ua = Q.shape.ua;
+      unit = ua * __umulhi((m >> 1) + ua - 1, Q.magic_ua);
+      k = 2;
+      c = p >= unit ? 1u : 0u;
+    } else {
+      unit = kd == kLower ? Q.shape.l : Q.shape.la;
+      const uint32_t mg = kd == kLower ? Q.magic_l : Q.magic_la;
+      k = __umulhi(m + unit - 1, mg);
+      c = __umulhi(p, mg);
     }
-    skip_ones(Q.gr, &up, skip_nodes, end);
-    m = part_size(pr, c);
+    offset += (uint64_t)c * unit;
+    fp += (uint64_t)c * Q.fixedbits[unit];
+    skip_ones(Q.gr, &up, (uint64_t)c * Q.nodecnt[unit], end);
+    m = c + 1 < k ? unit : m - (k - 1) * unit;
     depth += 1;
   }
   out[idx] = cj + offset + pos;
+}
+
+__global__ void k_decode_offsets(EFView C, EFView P, uint64_t N, uint64_t* out) {
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < N;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    out[2 * j] = ef_get(C, j);
+    out[2 * j + 1] = ef_get(P, j);
+  }
 }
 
 uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
@@ -276,6 +335,13 @@ hipError_t select_samples(const uint64_t* words, uint64_t nwords, uint64_t* coun
   hipError_t e = scan_excl_u64(counts, nwords, prefix, scan_tmp, s);
   if (e != hipSuccess) return e;
   k_samples<<<grid_for(nwords, 256, 8192), 256, 0, s>>>(words, nwords, prefix, samples, nsamples);
+  return hipGetLastError();
+}
+
+hipError_t decode_offsets(const EFView& C, const EFView& P, uint64_t N, uint64_t* out,
+                          hipStream_t s) {
+  if (!N) return hipSuccess;
+  k_decode_offsets<<<grid_for(N, 256, 8192), 256, 0, s>>>(C, P, N, out);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ hipError_t gr_write(const uint64_t* node_base, uint64_t nb, const uint64_t* vals
 hipError_t ef_write(const uint64_t* x, uint64_t N, uint32_t L, uint64_t* lower, uint64_t* upper,
                     hipStream_t s);
 
-// Select support: every 256th one of a bit vector.
+// Select support: every 2^kSampleShift-th one of a bit vector.
 hipError_t select_samples(const uint64_t* words, uint64_t nwords, uint64_t* scratch_counts,
                           uint64_t* scratch_prefix, uint64_t* scan_tmp, uint64_t* samples,
                           uint64_t nsamples, hipStream_t s);
@@ -71,8 +71,15 @@ struct EFView {
   uint32_t L;
 };
 
+// One select sample (the position of a one) every 2^kSampleShift ones of an
+// Elias-Fano upper vector.
+constexpr uint32_t kSampleShift = 5;
+
 struct QueryParams {
   EFView C, P;
+  // the two sequences decoded, (C_j, P_j) for j = 0..nb, or null: read them
+  // through C and P
+  const uint64_t* offsets;
   const uint64_t* gr;
   uint64_t gr_bits;
   uint64_t nb;
@@ -82,9 +89,14 @@ struct QueryParams {
   const uint32_t* fixedbits;
   const uint8_t* tau;
   const uint64_t* start;
+  // ceil(2^32 / d) for d = l, la, ua: exact quotients of numerators below 2^14
+  uint32_t magic_l, magic_la, magic_ua;
 };
 
 hipError_t launch_query(const QueryParams& q, const Key* keys, uint64_t n, uint64_t* out,
                         hipStream_t s);
+// out[2j] = C_j, out[2j+1] = P_j for j < N (both sequences hold N elements).
+hipError_t decode_offsets(const EFView& C, const EFView& P, uint64_t N, uint64_t* out,
+                          hipStream_t s);
 
 }  // namespace rs

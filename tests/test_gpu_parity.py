@@ -81,6 +81,18 @@ def test_non_members_match_oracle():
     assert np.array_equal(f.query(other), oracle.query(data, other))
 
 
+def test_query_through_elias_fano_selects():
+    """A query reads the bucket offsets C_j, C_j+1 and the record offset P_j
+    from a decoded copy of both Elias-Fano sequences when that copy is no
+    larger than the structure (or 1 MiB), else by select on the sequences
+    themselves.  80 000 buckets of 5 keys take the select path (1.28 MB of
+    offsets against 0.16 MB of structure)."""
+    keys = keygen.fingerprints(400_000, 31)
+    f, data = _check_parity(keys, 5, 5, True, "select path")
+    other = keygen.fingerprints(50_000, 32)
+    assert np.array_equal(f.query(other), oracle.query(data, other))
+
+
 def test_device_keys_and_determinism():
     import torch
 
