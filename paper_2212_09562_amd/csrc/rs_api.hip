@@ -221,11 +221,6 @@ struct Carver {
   }
 };
 
-hipError_t h2d(Context& c, void* dst, const void* src, size_t bytes) {
-  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.s);
-  return e == hipSuccess ? hipStreamSynchronize(c.s) : e;
-}
-
 hipError_t d2h(Context& c, void* dst, const void* src, size_t bytes) {
   hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.s);
   return e == hipSuccess ? hipStreamSynchronize(c.s) : e;
@@ -253,9 +248,11 @@ struct rs_mphf {
   int device = 0;
   std::mutex dev_mu;  // guards the lazily made device copy
   bool dev_ready = false;
-  uint64_t* d_words = nullptr;
-  uint64_t* d_samples = nullptr;  // samples of C, then of P
-  uint64_t* d_offsets = nullptr;  // (C_j, P_j) decoded, when no larger than the words
+  bool encoded = false;  // made by this library's encoder (not deserialised)
+  uint64_t* d_mem = nullptr;      // the device copy, one allocation:
+  uint64_t* d_words = nullptr;    //   the words,
+  uint64_t* d_samples = nullptr;  //   select samples of C, then of P,
+  uint64_t* d_offsets = nullptr;  //   (C_j, P_j) decoded, when no larger than the words
   uint64_t ns_c = 0, ns_p = 0;
   rs_stats stats{};
   std::vector<uint64_t> keep_vals, keep_base;
@@ -363,9 +360,7 @@ bool job_args_ok(const rs_key128* keys, uint64_t n, uint32_t l, uint32_t b, uint
 
 void mphf_release(rs_mphf* f) {
   if (!f) return;
-  if (f->d_words) (void)hipFree(f->d_words);
-  if (f->d_samples) (void)hipFree(f->d_samples);
-  if (f->d_offsets) (void)hipFree(f->d_offsets);
+  if (f->d_mem) (void)hipFree(f->d_mem);
   delete f;
 }
 
@@ -424,14 +419,33 @@ void ef_views(const rs_mphf* f, EFView* C, EFView* P) {
 
 int attach_device(Context& c, rs_mphf* f) {
   const uint64_t nw = f->words.size();
-  f->d_words = nullptr;
-  f->d_samples = nullptr;
-  f->d_offsets = nullptr;
-  HIPCHECK(hipMalloc(&f->d_words, nw * sizeof(uint64_t)));
-  HIPCHECK(h2d(c, f->d_words, f->words.data(), nw * sizeof(uint64_t)));
   f->ns_c = (f->efc.N + (1u << kSampleShift) - 1) >> kSampleShift;
   f->ns_p = (f->efp.N + (1u << kSampleShift) - 1) >> kSampleShift;
-  HIPCHECK(hipMalloc(&f->d_samples, (f->ns_c + f->ns_p + 2) * sizeof(uint64_t)));
+  // Both sequences decoded into one array when it is no larger than the
+  // structure (or 1 MiB): a query then reads C_j, P_j and C_{j+1} with two
+  // loads instead of three selects.
+  const uint64_t N = f->efc.N;
+  const bool decode = N == f->efp.N && N * 16 <= (nw * 8 > (1u << 20) ? nw * 8 : (1u << 20));
+  // one allocation: the words, the samples, the decoded pairs
+  const uint64_t ns = f->ns_c + f->ns_p + 2;
+  f->d_mem = nullptr;
+  HIPCHECK(hipMalloc(&f->d_mem, (nw + ns + (decode ? 2 * N : 0)) * sizeof(uint64_t)));
+  f->d_words = f->d_mem;
+  f->d_samples = f->d_mem + nw;
+  f->d_offsets = decode ? f->d_samples + ns : nullptr;
+  HIPCHECK(hipMemcpyAsync(f->d_words, f->words.data(), nw * sizeof(uint64_t),
+                          hipMemcpyHostToDevice, c.s));
+  if (decode && f->encoded) {
+    // the encoder's own sequences: decoded in one launch, no select support
+    // (the query reads only the pairs)
+    EFView C, P;
+    ef_views(f, &C, &P);
+    HIPCHECK(decode_pairs(C, f->efc.uw, P, f->efp.uw, f->d_offsets, c.s));
+    HIPCHECK(hipStreamSynchronize(c.s));
+    f->device = c.dev->id;
+    f->dev_ready = true;
+    return RS_OK;
+  }
   const EFLayout* efs[2] = {&f->efc, &f->efp};
   uint64_t* samp[2] = {f->d_samples, f->d_samples + f->ns_c};
   uint64_t nsamp[2] = {f->ns_c, f->ns_p};
@@ -444,20 +458,22 @@ int attach_device(Context& c, rs_mphf* f) {
     uint64_t* prefix = static_cast<uint64_t*>(c.sc_prefix.p);
     HIPCHECK(select_samples(upper, e.uw, static_cast<uint64_t*>(c.sc_counts.p), prefix,
                             static_cast<uint64_t*>(c.sc_tmp.p), samp[i], nsamp[i], c.s));
-    uint64_t ones = 0;
-    if (e.uw) HIPCHECK(d2h(c, &ones, prefix + e.uw, sizeof ones));
-    if (ones != e.N) return RS_ERR_CORRUPT;
+    // Bytes from outside (rs_deserialize) must hold exactly N ones in each
+    // upper vector before a select may run over them; the encoder's own
+    // words need no check (and no wait).
+    if (!f->encoded) {
+      uint64_t ones = 0;
+      if (e.uw) HIPCHECK(d2h(c, &ones, prefix + e.uw, sizeof ones));
+      if (ones != e.N) return RS_ERR_CORRUPT;
+    }
   }
-  // Both sequences decoded into one array when it is no larger than the
-  // structure (or 1 MiB): a query then reads C_j, P_j and C_{j+1} with two
-  // loads instead of three selects.
-  const uint64_t N = f->efc.N;
-  if (N == f->efp.N && N * 16 <= (nw * 8 > (1u << 20) ? nw * 8 : (1u << 20))) {
-    HIPCHECK(hipMalloc(&f->d_offsets, N * 16));
+  if (decode) {
     EFView C, P;
     ef_views(f, &C, &P);
     HIPCHECK(decode_offsets(C, P, N, f->d_offsets, c.s));
   }
+  // complete before any other stream may query the copy
+  HIPCHECK(hipStreamSynchronize(c.s));
   f->device = c.dev->id;
   f->dev_ready = true;
   return RS_OK;
@@ -582,6 +598,7 @@ void encode_words(Context& c, const Arrays& A, std::vector<JobPlan>& jobs,
     f->gr_at = o.gr_at;
     f->gr_bits = o.gr_bits;
     f->gr_words = o.gr_words;
+    f->encoded = true;
     f->words.assign(o.nw, 0);
     o.f = f;
     o.hw = f->words.data();
@@ -1174,10 +1191,10 @@ int rs_query(const rs_mphf* f, const rs_key128* keys, uint64_t n, uint64_t* out,
     if (!g->dev_ready) {
       rc = attach_device(*c, g);
       if (rc) {
-        if (g->d_words) (void)hipFree(g->d_words);
-        if (g->d_samples) (void)hipFree(g->d_samples);
-        if (g->d_offsets) (void)hipFree(g->d_offsets);
-        g->d_words = g->d_samples = g->d_offsets = nullptr;
+        // (the stream is drained before the copy is freed)
+        (void)hipStreamSynchronize(c->s);
+        if (g->d_mem) (void)hipFree(g->d_mem);
+        g->d_mem = g->d_words = g->d_samples = g->d_offsets = nullptr;
         return rc;
       }
     } else if (g->device != d.id) {

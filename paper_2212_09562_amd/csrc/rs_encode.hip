@@ -300,6 +300,51 @@ __global__ void k_decode_offsets(EFView C, EFView P, uint64_t N, uint64_t* out) 
   }
 }
 
+// Both sequences decoded without select support, one block per sequence
+// (block 0: C into out[2i], block 1: P into out[2i+1]).  The upper vector is
+// read in slices of one word per thread; a block prefix sum of the words'
+// popcounts numbers the ones, and the one numbered i at bit position p gives
+// element i = ((p - i) << L) | its L lower bits.
+constexpr uint32_t kDecodeThreads = 1024;
+
+__global__ void __launch_bounds__(kDecodeThreads) k_decode_pairs(EFView C, uint64_t c_words,
+                                                                 EFView P, uint64_t p_words,
+                                                                 uint64_t* out) {
+  __shared__ uint32_t s_wave[kDecodeThreads / 64];
+  const uint32_t which = blockIdx.x;
+  const EFView e = which ? P : C;
+  const uint64_t nwords = which ? p_words : c_words;
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+  uint64_t base = 0;  // ones in the slices before this one
+  for (uint64_t w0 = 0; w0 < nwords; w0 += kDecodeThreads) {
+    const uint64_t wi = w0 + threadIdx.x;
+    uint64_t word = wi < nwords ? e.upper[wi] : 0;
+    const uint32_t c = (uint32_t)__popcll(word);
+    uint32_t incl = c;  // inclusive prefix sum within the wave
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d);
+      if (lane >= d) incl += o;
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (uint32_t w = 0; w < kDecodeThreads / 64; ++w) {
+      if (w < wave) before += s_wave[w];
+      total += s_wave[w];
+    }
+    uint64_t i = base + before + incl - c;
+    while (word) {
+      const uint64_t p = wi * 64 + (uint64_t)__builtin_ctzll(word);
+      if (i < e.N) out[2 * i + which] = ((p - i) << e.L) | read_bits(e.lower, i * e.L, e.L);
+      ++i;
+      word &= word - 1;
+    }
+    base += total;
+    __syncthreads();  // s_wave is rewritten by the next slice
+  }
+}
+
 uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
   uint64_t g = (n + threads - 1) / threads;
   if (g > cap) g = cap;
@@ -342,6 +387,12 @@ hipError_t decode_offsets(const EFView& C, const EFView& P, uint64_t N, uint64_t
                           hipStream_t s) {
   if (!N) return hipSuccess;
   k_decode_offsets<<<grid_for(N, 256, 8192), 256, 0, s>>>(C, P, N, out);
+  return hipGetLastError();
+}
+
+hipError_t decode_pairs(const EFView& C, uint64_t c_words, const EFView& P, uint64_t p_words,
+                        uint64_t* out, hipStream_t s) {
+  k_decode_pairs<<<2, kDecodeThreads, 0, s>>>(C, c_words, P, p_words, out);
   return hipGetLastError();
 }
 

@@ -95,8 +95,12 @@ struct QueryParams {
 
 hipError_t launch_query(const QueryParams& q, const Key* keys, uint64_t n, uint64_t* out,
                         hipStream_t s);
-// out[2j] = C_j, out[2j+1] = P_j for j < N (both sequences hold N elements).
+// out[2j] = C_j, out[2j+1] = P_j for j < N (both sequences hold N elements):
+// through select samples, or (decode_pairs) straight from upper vectors of
+// c_words and p_words words that hold exactly N ones each.
 hipError_t decode_offsets(const EFView& C, const EFView& P, uint64_t N, uint64_t* out,
                           hipStream_t s);
+hipError_t decode_pairs(const EFView& C, uint64_t c_words, const EFView& P, uint64_t p_words,
+                        uint64_t* out, hipStream_t s);
 
 }  // namespace rs

@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_out(const T* in, uint64_t
 #pragma unroll
   for (uint32_t i = 0; i < kScanPer; ++i) v[i] = base + i < n ? (uint64_t)in[base + i] : 0;
   const uint64_t total = block_excl_scan(v, s_wave);
-  const uint64_t add = sums[blockIdx.x];
+  const uint64_t add = sums ? sums[blockIdx.x] : 0;  // null: a single block
 #pragma unroll
   for (uint32_t i = 0; i < kScanPer; ++i)
     if (base + i < n) out[base + i] = v[i] + add;
@@ -301,6 +301,10 @@ template <typename T>
 static hipError_t scan_impl(const T* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s) {
   if (n == 0) return fill_u64(out, 1, 0, s);
   const uint64_t nblocks = (n + kScanBlock - 1) / kScanBlock;
+  if (nblocks == 1) {  // one block holds everything: one launch
+    k_scan_out<T><<<1, kScanThreads, 0, s>>>(in, n, nullptr, out);
+    return hipGetLastError();
+  }
   k_scan_sums<T><<<(uint32_t)nblocks, kScanThreads, 0, s>>>(in, n, tmp);
   k_scan_top<<<1, kScanThreads, 0, s>>>(tmp, nblocks);
   k_scan_out<T><<<(uint32_t)nblocks, kScanThreads, 0, s>>>(in, n, tmp, out);
