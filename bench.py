@@ -493,6 +493,8 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--per-launch", type=int, default=8)
     ap.add_argument("--reserve-per-cu", type=int, default=0)
+    ap.add_argument("--small-only", action="store_true",
+                    help="instead: only the two l = 8, b = 100 workloads")
     ap.add_argument("--served-only", action="store_true",
                     help="instead: only the served workload (with --budget-gib, --slots, "
                          "--per-launch, --reserve-per-cu)")
@@ -534,6 +536,12 @@ def main():
         print(json.dumps({"served": run_served(recsplit, keygen, torch, args.served_requests,
                                                args.budget_gib, args.slots, args.per_launch,
                                                args.reserve_per_cu)}), flush=True)
+        return
+    if args.small_only:
+        rates = recsplit.calibrate_valu()
+        print(json.dumps({"small_configs": {
+            name: run_small_config(recsplit, keygen, torch, sn, seed, srot, rates)
+            for name, sn, seed, srot in SMALL_CONFIGS}}), flush=True)
         return
     if args.single:
         for l, b, n in args.single:
