@@ -400,9 +400,6 @@ size_t batch_footprint(const std::vector<JobPlan>& jobs, uint32_t workers_max) {
 
 namespace {
 
-// Device copy of the serialised words plus select samples of both upper
-// vectors; checks that each upper vector holds exactly N ones.  Caller holds
-// f->dev_mu.
 // The device views of the two Elias-Fano sequences of an attached structure.
 void ef_views(const rs_mphf* f, EFView* C, EFView* P) {
   C->lower = f->d_words + f->efc.at + kEfHeaderWords;
@@ -417,6 +414,10 @@ void ef_views(const rs_mphf* f, EFView* C, EFView* P) {
   P->L = (uint32_t)f->efp.L;
 }
 
+// The device copy a query reads: the serialised words, and the bucket
+// offsets decoded into pairs or select samples of both upper vectors;
+// deserialised words are checked to hold exactly N ones in each upper vector.
+// Caller holds f->dev_mu.
 int attach_device(Context& c, rs_mphf* f) {
   const uint64_t nw = f->words.size();
   f->ns_c = (f->efc.N + (1u << kSampleShift) - 1) >> kSampleShift;
