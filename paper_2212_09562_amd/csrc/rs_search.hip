@@ -466,12 +466,16 @@ __device__ void run_leaf_filtered(const Node& c, uint64_t first, uint32_t rounds
 // per wave; an entry is (index << 32) | counters.
 // Counters: the first k-1 children in fields of fe bits, fe the bit length
 // of the part size, so a field holds its part size without carrying; the
-// last child (its count follows from the total) is added above them and
-// ignored.  A field above its part size carries out when (part-size
-// complement) is added to every field, which one add and two xors expose for
-// all fields at once; a field that has wrapped is only a missed early exit.
-// The final word test is exact for attempts without a carry, and every match
-// is verified exactly before it counts.
+// last child is added above them and not counted.  A field above its part
+// size carries out when (part-size complement) is added to every field,
+// which one add and two xors expose for all fields at once; a field that has
+// wrapped is only a missed early exit.  With 32-bit counters each stage end
+// also tests the last child, whose count is the keys so far minus the sum of
+// the fields (added by one multiply), against its part size: without that
+// test twice as many attempts reach the last stage (11 % of the lower-split
+// attempts against 5.5 %, 19 % of the upper ones against 8.6 %).  The final
+// word test is exact for attempts without a carry, and every match is
+// verified exactly before it counts.
 constexpr uint32_t kMinFilterRounds = 8;  // shorter chunks: the plain rounds
 
 // Counter words: 32 bits where the k-1 fields fit (up to l = 18), else 64
@@ -485,6 +489,10 @@ struct SplitFilter {
   static constexpr uint64_t kAccMask = sizeof(T) == 4 ? 0xFFFFFFFFull : (1ull << 50) - 1;
   uint32_t fe, b1, b2, b3;
   T target, comp, carries, low;
+  // 32-bit counters: the sum of the counted fields, for the test of the last
+  // child (pairs of fields into slots of 2 fe bits, then one multiply adds
+  // the slots into the top one)
+  uint32_t pairs, slots, slot_at;
 };
 
 template <typename T>
@@ -505,6 +513,12 @@ __device__ __forceinline__ SplitFilter<T> make_split_filter(const Node& c) {
     f.carries |= (T)1 << (f.fe * (j + 1));
   }
   f.low = ((T)1 << (f.fe * (c.k - 1))) - 1u;
+  f.pairs = f.slots = f.slot_at = 0;
+  for (uint32_t j = 0; j + 1 < c.k; j += 2) {
+    f.pairs |= ((1u << f.fe) - 1u) << (f.fe * j);
+    f.slot_at = f.fe * j;
+    f.slots |= 1u << f.slot_at;
+  }
   // Stage ends, as fractions of m chosen per node kind from the law of the
   // key at which an attempt dies (simulated for 7 parts of 16 and 5 parts
   // of 112; a queue hand-off counted as one more key): lower splits die
@@ -555,6 +569,18 @@ __device__ void run_split_filtered(const uint64_t* keys, const Node& c, uint64_t
   uint32_t w1 = 0, w2 = 0, w3 = 0;  // rounds the oldest entry of each queue has waited
   auto attempt_of = [&](uint64_t idx) { return (idx >> 6) * kWG + lane_base + (idx & 63u); };
   auto alive = [&](T acc) { return (((acc + f.comp) ^ acc ^ f.comp) & f.carries) == 0; };
+  // alive, and the last child (its count is the keys so far minus the
+  // counted fields) not above its part size
+  auto alive_at = [&](T acc, uint32_t keys_done) {
+    if constexpr (sizeof(T) == 4) {
+      const uint32_t a = (uint32_t)(acc & f.low);  // without the last child's bits
+      const uint32_t t = (a & f.pairs) + ((a >> f.fe) & f.pairs);
+      const uint32_t sum = (uint32_t)(((uint64_t)t * f.slots) >> f.slot_at) & ((1u << (2 * f.fe)) - 1u);
+      return alive(acc) && sum + c.last >= keys_done;
+    } else {
+      return alive(acc);
+    }
+  };
   auto pack = [&](uint64_t idx, T acc) { return (idx << F::kIdxShift) | ((uint64_t)acc & F::kAccMask); };
   // stages 2 and 3: the next key range for up to 64 entries of queue qi,
   // survivors to queue qo
@@ -566,7 +592,7 @@ __device__ void run_split_filtered(const uint64_t* keys, const Node& c, uint64_t
     const uint64_t idx = e >> F::kIdxShift;
     const T acc = split_count<T>(keys, c, f.fe, lo, hi, c.start + attempt_of(idx),
                                  (T)(e & F::kAccMask));
-    queue_push(qo, to, v && alive(acc), pack(idx, acc));
+    queue_push(qo, to, v && alive_at(acc, hi), pack(idx, acc));
   };
   // stage 4: the last keys, the word test, exact verification in order
   auto last = [&](uint32_t cnt) -> uint64_t {
@@ -591,7 +617,7 @@ __device__ void run_split_filtered(const uint64_t* keys, const Node& c, uint64_t
         uni64(__hip_atomic_load(s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
     if (a0 >= cur) break;
     const T acc = split_count<T>(keys, c, f.fe, 0, f.b1, c.start + a0 + lane, (T)0);
-    queue_push(q1, t1, alive(acc), pack((uint64_t)r * 64u + lane, acc));
+    queue_push(q1, t1, alive_at(acc, f.b1), pack((uint64_t)r * 64u + lane, acc));
     w1 = t1 != h1 ? w1 + 1 : 0;
     if (t1 - h1 >= 64 || (t1 != h1 && w1 >= patience)) {
       middle(q1, h1, q2, t2, t1 - h1 < 64 ? t1 - h1 : 64, f.b1, f.b2);
