@@ -779,11 +779,17 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
                               hipMemcpyHostToDevice, s));
   HIPCHECK(hipEventRecord(c.ev[1], s));
 
-  // 1. buckets: sizes, borders, scatter, duplicate check, node counts
+  // 1. buckets: sizes, borders, scatter, duplicate check, node counts, with
+  // one wait for all of them.  The duplicate check's LDS is sized before the
+  // bucket sizes are known, from the expected bucket size (b + 8 sqrt(b) + 32
+  // keys, rounded up to a power of two, within the LDS of a block); a bucket
+  // beyond it is checked after the wait, with a second one.
   HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(A.ctl), sizeof(Control) / 8, 0, s));
   HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(A.jinfo), nj * sizeof(JobInfo) / 8, 0, s));
   HIPCHECK(fill_u32(A.cnt, nbk, 0, s));
   HIPCHECK(fill_u32(A.fill, nbk, 0, s));
+  uint32_t lds_keys = 1;  // the largest power of two of keys a block can sort
+  while ((uint64_t)lds_keys * 2 * 8 + 1024 <= (uint64_t)d.lds_per_block) lds_keys *= 2;
   for (uint32_t i = 0; i < nj; ++i) {
     JobPlan& j = jobs[i];
     if (j.status) continue;
@@ -793,9 +799,19 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     HIPCHECK(bucket_histogram(kin, j.n, j.nb, cnt, &A.jinfo[i].maxm, s));
     HIPCHECK(scan_excl_u32(cnt, j.nb, off, A.tmp, s));
     HIPCHECK(bucket_scatter(kin, j.n, j.nb, off, A.fill + j.bucket_base, A.k0 + j.key_base, s));
+    const double want = j.b + 8.0 * sqrt((double)j.b) + 32.0;
+    uint32_t cap = 64;
+    while (cap < want && cap < lds_keys) cap *= 2;
+    HIPCHECK(duplicate_check(A.k0 + j.key_base, off, j.nb, cap, &A.jinfo[i].error,
+                             &A.jinfo[i].deferred, s));
+    HIPCHECK(node_counts(cnt, j.nb, j.T->nodecnt, A.nodes + j.bucket_base, s));
+    HIPCHECK(scan_excl_u64(A.nodes + j.bucket_base, j.nb, A.node_base + j.off_base, A.tmp, s));
+    HIPCHECK(hipMemcpyAsync(&A.jinfo[i].nodes, A.node_base + j.off_base + j.nb, sizeof(uint64_t),
+                            hipMemcpyDeviceToDevice, s));
   }
   std::vector<JobInfo> hinfo(nj);
   HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
+  bool again = false;
   for (uint32_t i = 0; i < nj; ++i) {
     JobPlan& j = jobs[i];
     if (j.status) continue;
@@ -807,14 +823,13 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
       j.status = RS_ERR_UNSUPPORTED;
       continue;
     }
-    HIPCHECK(duplicate_check(A.k0 + j.key_base, A.off + j.off_base, j.nb, j.maxm,
-                             &A.jinfo[i].error, s));
-    HIPCHECK(node_counts(A.cnt + j.bucket_base, j.nb, j.T->nodecnt, A.nodes + j.bucket_base, s));
-    HIPCHECK(scan_excl_u64(A.nodes + j.bucket_base, j.nb, A.node_base + j.off_base, A.tmp, s));
-    HIPCHECK(hipMemcpyAsync(&A.jinfo[i].nodes, A.node_base + j.off_base + j.nb, sizeof(uint64_t),
-                            hipMemcpyDeviceToDevice, s));
+    if (hinfo[i].deferred && !hinfo[i].error) {
+      HIPCHECK(duplicate_check(A.k0 + j.key_base, A.off + j.off_base, j.nb, p2,
+                               &A.jinfo[i].error, &A.jinfo[i].deferred, s));
+      again = true;
+    }
   }
-  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
+  if (again) HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
   uint64_t total = 0;
   uint32_t maxm = 0;
   for (uint32_t i = 0; i < nj; ++i) {
@@ -976,15 +991,17 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   }
   HIPCHECK(hipEventRecord(c.ev[4], s));
   if (progress > 0.0) wait_with_progress(c, total, progress);
-  // useful work of every job, counted from its node values (harmless after a
-  // stopped search, whose results are dropped), read back with the control
-  // block in one wait
+  // useful work of every job, counted from its node values, and the length
+  // of every bucket's record (both harmless after a stopped search, whose
+  // results are dropped), read back with the control block in one wait
   for (uint32_t i = 0; i < nj; ++i) {
     const JobPlan& j = jobs[i];
     if (j.status || !j.total) continue;
     HIPCHECK(work_counts(A.vals + j.node_off, A.msz + j.node_off, j.total, j.l,
                          (j.flags & RS_FLAG_ROTATION) ? 1u : 0u, j.T->split_work, A.jinfo + i, s));
   }
+  const int enc_rc = encode_lengths(c, A, jobs);
+  if (enc_rc) return enc_rc;
   Control h_ctl;
   HIPCHECK(hipMemcpyAsync(&h_ctl, A.ctl, sizeof h_ctl, hipMemcpyDeviceToHost, s));
   HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
@@ -1011,11 +1028,8 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     return RS_OK;
   }
 
-  // 3. encode every job that succeeded: record lengths (one wait for all
-  // jobs' record bits), then the words (one wait)
-  const int enc_rc = encode_lengths(c, A, jobs);
-  if (enc_rc) return enc_rc;
-  HIPCHECK(d2h(c, hinfo.data(), A.jinfo, nj * sizeof(JobInfo)));
+  // 3. encode every job that succeeded (its record bits came with the
+  // status): the words (one wait)
   encode_words(c, A, jobs, hinfo, ms_sort, ms_search, workers);
   return RS_OK;
 }

@@ -142,6 +142,8 @@ struct JobInfo {
   uint64_t early_exit_split_fx;  // the same for splits (split_work_table)
   uint64_t nodes;    // stored nodes of the job (copied from its node-count scan)
   uint64_t gr_bits;  // bits of its Golomb-Rice records (copied from their scan)
+  uint32_t deferred;  // some bucket was too large for the first duplicate check
+  uint32_t pad;
 };
 
 // Expected hash evaluations of one failed leaf attempt of size m when the

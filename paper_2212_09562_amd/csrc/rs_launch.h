@@ -19,8 +19,10 @@ hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* 
                             hipStream_t s);
 hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
                           uint32_t* fill, Key* out, hipStream_t s);
-hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t maxm,
-                           uint32_t* error, hipStream_t s);
+// cap: LDS words of the check (a power of two); buckets whose next power of
+// two exceeds it are skipped and set *deferred.
+hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t cap,
+                           uint32_t* error, uint32_t* deferred, hipStream_t s);
 hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s);
 hipError_t node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* nodecnt, uint64_t* out,
                        hipStream_t s);

@@ -147,9 +147,11 @@ __global__ void k_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64
 
 // Two keys of a bucket with equal w1 hash alike under every seed, so their
 // leaf could never be a bijection: sort the bucket's w1 words (bitonic, in
-// LDS) and compare neighbours.
+// LDS) and compare neighbours.  Buckets that need more than `cap` words of
+// LDS are skipped and reported in *deferred.
 __global__ void __launch_bounds__(256) k_dupcheck(const Key* keys, const uint64_t* off, uint64_t nb,
-                                                  uint32_t* error) {
+                                                  uint32_t cap, uint32_t* error,
+                                                  uint32_t* deferred) {
   extern __shared__ uint64_t s[];
   for (uint64_t j = blockIdx.x; j < nb; j += gridDim.x) {
     const uint64_t o = off[j];
@@ -157,6 +159,10 @@ __global__ void __launch_bounds__(256) k_dupcheck(const Key* keys, const uint64_
     if (m < 2) continue;
     uint32_t p2 = 1;
     while (p2 < m) p2 <<= 1;
+    if (p2 > cap) {
+      if (threadIdx.x == 0) atomicOr(deferred, 1u);
+      continue;
+    }
     for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) s[i] = i < m ? keys[o + i].w1 : ~0ull;
     __syncthreads();
     for (uint32_t k = 2; k <= p2; k <<= 1) {
@@ -252,7 +258,7 @@ __global__ void k_node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* 
                               uint64_t* out) {
   for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nb;
        j += (uint64_t)gridDim.x * blockDim.x)
-    out[j] = nodecnt[cnt[j]];
+    out[j] = cnt[j] <= kMaxBucketKeys ? nodecnt[cnt[j]] : 0;  // larger: refused later
 }
 
 __global__ void k_roots(const uint32_t* cnt, const uint64_t* off, const uint64_t* node_base,
@@ -340,12 +346,11 @@ hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64
   return hipGetLastError();
 }
 
-hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t maxm,
-                           uint32_t* error, hipStream_t s) {
-  if (maxm < 2) return hipSuccess;
-  uint32_t p2 = 1;
-  while (p2 < maxm) p2 <<= 1;
-  k_dupcheck<<<grid_for(nb, 1, 4096), 256, p2 * sizeof(uint64_t), s>>>(keys, off, nb, error);
+hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t cap,
+                           uint32_t* error, uint32_t* deferred, hipStream_t s) {
+  if (cap < 2) return hipSuccess;
+  k_dupcheck<<<grid_for(nb, 1, 4096), 256, cap * sizeof(uint64_t), s>>>(keys, off, nb, cap, error,
+                                                                        deferred);
   return hipGetLastError();
 }
 

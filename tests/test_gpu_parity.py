@@ -330,6 +330,27 @@ def test_progress_lines(capfd):
     assert data == ref
 
 
+def _skewed(n, seed, nb, big):
+    """n keys whose first `big` fall into bucket 0 of nb (w0 below 2^64/nb)."""
+    keys = keygen.fingerprints(n, seed).copy()
+    keys[:big, 0] >>= np.uint64(8)
+    return keys
+
+
+def test_bucket_beyond_the_first_duplicate_check():
+    """The duplicate check's LDS is sized from the expected bucket size before
+    the sizes are known; a far larger bucket (600 keys where b = 100) is
+    checked after the first wait, with a second check sized to it."""
+    n, b = 3000, 100
+    keys = _skewed(n, 41, oracle.num_buckets(n, b), 600)
+    _check_parity(keys, 8, b, True, "one bucket of 600+ keys")
+    dup = keys.copy()
+    dup[599] = dup[3]  # two equal keys in the large bucket
+    with pytest.raises(rs().RecSplitError) as e:
+        rs().build(dup, 8, b, True)
+    assert e.value.code == -2
+
+
 def test_largest_buckets():
     _case("b=4096, n=12000, l=8")
     _check_parity(keygen.fingerprints(12000, 15), 8, 4096, True)
