@@ -786,33 +786,24 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
   // beyond it is checked after the wait, with a second one.
   HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(A.ctl), sizeof(Control) / 8, 0, s));
   HIPCHECK(fill_u64(reinterpret_cast<uint64_t*>(A.jinfo), nj * sizeof(JobInfo) / 8, 0, s));
-  bool atomics = false;  // some job's sort counts with device-wide atomics, from zero
-  for (const JobPlan& j : jobs)
-    if (!j.status && bucket_rows_words(j.n, j.nb) == 0) atomics = true;
-  if (atomics) {
-    HIPCHECK(fill_u32(A.cnt, nbk, 0, s));
-    HIPCHECK(fill_u32(A.fill, nbk, 0, s));
-  }
-  uint32_t lds_keys = 1;  // the largest power of two of keys a block can check (two words a key)
-  while ((uint64_t)lds_keys * 2 * 2 * 8 <= (uint64_t)d.lds_per_block) lds_keys *= 2;
+  HIPCHECK(fill_u32(A.cnt, nbk, 0, s));
+  HIPCHECK(fill_u32(A.fill, nbk, 0, s));
+  uint32_t lds_keys = 1;  // the largest power of two of keys a block can sort
+  while ((uint64_t)lds_keys * 2 * 8 + 1024 <= (uint64_t)d.lds_per_block) lds_keys *= 2;
   for (uint32_t i = 0; i < nj; ++i) {
     JobPlan& j = jobs[i];
     if (j.status) continue;
     const Key* kin = (j.flags & RS_FLAG_KEYS_ON_DEVICE) ? j.keys : A.keys_in + j.host_base;
     uint32_t* cnt = A.cnt + j.bucket_base;
     uint64_t* off = A.off + j.off_base;
-    // the chunked sort's rows in the job's part of the second key array (4n
-    // words; the rows take at most n), unused until the search
-    uint32_t* rows = reinterpret_cast<uint32_t*>(A.k1 + j.key_base);
-    HIPCHECK(bucket_histogram(kin, j.n, j.nb, rows, cnt, &A.jinfo[i].maxm, s));
+    HIPCHECK(bucket_histogram(kin, j.n, j.nb, cnt, &A.jinfo[i].maxm, s));
     HIPCHECK(scan_excl_u32(cnt, j.nb, off, A.tmp, s));
-    HIPCHECK(bucket_scatter(kin, j.n, j.nb, rows, off, A.fill + j.bucket_base, A.k0 + j.key_base,
-                            s));
+    HIPCHECK(bucket_scatter(kin, j.n, j.nb, off, A.fill + j.bucket_base, A.k0 + j.key_base, s));
     const double want = j.b + 8.0 * sqrt((double)j.b) + 32.0;
     uint32_t cap = 64;
     while (cap < want && cap < lds_keys) cap *= 2;
-    HIPCHECK(duplicate_check(A.k0 + j.key_base, off, j.nb, cap, (uint32_t)d.lds_per_block,
-                             &A.jinfo[i].error, &A.jinfo[i].deferred, s));
+    HIPCHECK(duplicate_check(A.k0 + j.key_base, off, j.nb, cap, &A.jinfo[i].error,
+                             &A.jinfo[i].deferred, s));
     HIPCHECK(node_counts(cnt, j.nb, j.T->nodecnt, A.nodes + j.bucket_base, s));
     HIPCHECK(scan_excl_u64(A.nodes + j.bucket_base, j.nb, A.node_base + j.off_base, A.tmp, s));
     HIPCHECK(hipMemcpyAsync(&A.jinfo[i].nodes, A.node_base + j.off_base + j.nb, sizeof(uint64_t),
@@ -834,8 +825,7 @@ int build_jobs(Context& c, std::vector<JobPlan>& jobs, void* region, size_t regi
     }
     if (hinfo[i].deferred && !hinfo[i].error) {
       HIPCHECK(duplicate_check(A.k0 + j.key_base, A.off + j.off_base, j.nb, p2,
-                               (uint32_t)d.lds_per_block, &A.jinfo[i].error,
-                               &A.jinfo[i].deferred, s));
+                               &A.jinfo[i].error, &A.jinfo[i].deferred, s));
       again = true;
     }
   }

@@ -15,22 +15,14 @@ uint64_t scan_tmp_words(uint64_t n);
 hipError_t scan_excl_u32(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
 hipError_t scan_excl_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
 
-// Counting sort of keys by bucket: sizes (cnt, the largest into *maxm), then,
-// given the exclusive scan of the sizes (off), the keys in bucket order.
-// rows: scratch of bucket_rows_words(n, nb) words, untouched between the two
-// calls (null, or no words needed: both count with device-wide atomics, the
-// scatter through fill, zeroed by the caller; cnt zeroed too).
-uint64_t bucket_rows_words(uint64_t n, uint64_t nb);
-hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* rows,
-                            uint32_t* cnt, uint32_t* maxm, hipStream_t s);
-hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint32_t* rows,
-                          const uint64_t* off, uint32_t* fill, Key* out, hipStream_t s);
-// cap: the most keys a checked bucket may hold; larger buckets are skipped
-// and set *deferred.  lds_bytes: the LDS one block may use (at least 8 bytes
-// a key of cap).
+hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, uint32_t* maxm,
+                            hipStream_t s);
+hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
+                          uint32_t* fill, Key* out, hipStream_t s);
+// cap: LDS words of the check (a power of two); buckets whose next power of
+// two exceeds it are skipped and set *deferred.
 hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t cap,
-                           uint32_t lds_bytes, uint32_t* error, uint32_t* deferred,
-                           hipStream_t s);
+                           uint32_t* error, uint32_t* deferred, hipStream_t s);
 hipError_t init_states(TaskState* st, uint64_t n, hipStream_t s);
 hipError_t node_counts(const uint32_t* cnt, uint64_t nb, const uint32_t* nodecnt, uint64_t* out,
                        hipStream_t s);

@@ -13,13 +13,6 @@ namespace {
 constexpr uint32_t kScanThreads = 256;
 constexpr uint32_t kScanPer = 4;
 constexpr uint32_t kScanBlock = kScanThreads * kScanPer;
-// the chunked counting sort: buckets counted in one block's LDS, and rows
-// (chunks) per bucket, 16 waves of kChunkRowsPerWave
-constexpr uint64_t kChunkMaxBuckets = 16384;
-constexpr uint32_t kChunkRowsPerWave = 16;
-constexpr uint32_t kChunkMaxRows = 16 * kChunkRowsPerWave;
-constexpr uint32_t kChunkThreads = 1024;  // a block of the count and the scatter
-constexpr uint32_t kChunkPer = 4;         // keys in flight a thread
 
 __device__ __forceinline__ uint64_t bucket_of(uint64_t w0, uint64_t nb) { return __umul64hi(w0, nb); }
 
@@ -152,162 +145,47 @@ __global__ void k_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64
   }
 }
 
-// The counting sort in chunks, for up to kChunkMaxBuckets buckets: block r
-// takes keys [r*chunk, (r+1)*chunk), counts them per bucket in LDS and writes
-// its counts as row r of `rows` (rows x nb words); the per-bucket prefix over
-// the rows then gives every block its own start in every bucket, so the
-// scatter needs LDS atomics only (a device-wide atomic per key, all blocks on
-// the same few thousand words, is what bounds the plain scatter).
-__global__ void __launch_bounds__(kChunkThreads) k_chunk_counts(const Key* keys, uint64_t n,
-                                                                uint64_t nb, uint64_t chunk,
-                                                                uint32_t* rows) {
-  extern __shared__ uint32_t s_h[];
-  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) s_h[i] = 0;
-  __syncthreads();
-  const uint64_t lo = blockIdx.x * chunk;
-  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (uint64_t base = lo; base < hi; base += kChunkPer * blockDim.x) {
-    // kChunkPer loads in flight a thread (past the end: the last key, not counted)
-    uint64_t w0[kChunkPer];
-#pragma unroll
-    for (uint32_t u = 0; u < kChunkPer; ++u) {
-      const uint64_t i = base + threadIdx.x + (uint64_t)u * blockDim.x;
-      w0[u] = keys[i < hi ? i : hi - 1].w0;
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < kChunkPer; ++u)
-      if (base + threadIdx.x + (uint64_t)u * blockDim.x < hi)
-        atomicAdd(&s_h[bucket_of(w0[u], nb)], 1u);
-  }
-  __syncthreads();
-  uint32_t* r = rows + blockIdx.x * nb;
-  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) r[i] = s_h[i];
-}
-
-// Per bucket (a lane; 16 waves share the rows, kChunkRowsPerWave each): the
-// exclusive prefix of its counts over the rows, in place, its size into cnt,
-// and the largest size into *maxm.
-__global__ void __launch_bounds__(1024) k_chunk_prefix(uint32_t* rows, uint32_t nrows, uint64_t nb,
-                                                       uint32_t* cnt, uint32_t* maxm) {
-  __shared__ uint32_t s_part[16][64];
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t b = (uint64_t)blockIdx.x * 64 + lane;
-  const uint32_t r0 = wave * kChunkRowsPerWave;
-  uint32_t x[kChunkRowsPerWave];
-  uint32_t sum = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < kChunkRowsPerWave; ++k) {
-    x[k] = b < nb && r0 + k < nrows ? rows[(uint64_t)(r0 + k) * nb + b] : 0u;
-    sum += x[k];
-  }
-  s_part[wave][lane] = sum;
-  __syncthreads();
-  uint32_t run = 0, total = 0;
-  for (uint32_t w = 0; w < 16; ++w) {
-    const uint32_t v = s_part[w][lane];
-    run += w < wave ? v : 0u;
-    total += v;
-  }
-  if (b < nb) {
-#pragma unroll
-    for (uint32_t k = 0; k < kChunkRowsPerWave; ++k) {
-      if (r0 + k < nrows) rows[(uint64_t)(r0 + k) * nb + b] = run;
-      run += x[k];
-    }
-    if (wave == 0) cnt[b] = total;
-  }
-  if (wave == 0) {
-    uint32_t mx = b < nb ? total : 0u;
-    for (uint32_t d = 32; d > 0; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d));
-    if (lane == 0 && mx) atomicMax(maxm, mx);
-  }
-}
-
-// Block r places its chunk's keys from its own start in every bucket (bucket
-// offset plus the prefix of the earlier rows, all below 2^32).
-__global__ void __launch_bounds__(kChunkThreads) k_chunk_scatter(const Key* keys, uint64_t n,
-                                                                 uint64_t nb, uint64_t chunk,
-                                                                 const uint32_t* rows,
-                                                                 const uint64_t* off, Key* out) {
-  extern __shared__ uint32_t s_at[];
-  const uint32_t* r = rows + blockIdx.x * nb;
-  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) s_at[i] = (uint32_t)off[i] + r[i];
-  __syncthreads();
-  const uint64_t lo = blockIdx.x * chunk;
-  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (uint64_t base = lo; base < hi; base += kChunkPer * blockDim.x) {
-    Key k[kChunkPer];
-#pragma unroll
-    for (uint32_t u = 0; u < kChunkPer; ++u) {
-      const uint64_t i = base + threadIdx.x + (uint64_t)u * blockDim.x;
-      k[u] = keys[i < hi ? i : hi - 1];
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < kChunkPer; ++u)
-      if (base + threadIdx.x + (uint64_t)u * blockDim.x < hi)
-        out[atomicAdd(&s_at[bucket_of(k[u].w0, nb)], 1u)] = k[u];
-  }
-}
-
 // Two keys of a bucket with equal w1 hash alike under every seed, so their
-// leaf could never be a bijection.  Each wave takes one bucket at a time and
-// inserts every key's w1 into an open-addressing table of 2^tbits words in
-// its own part of the LDS (zero marks a free word; keys whose w1 is zero are
-// counted instead): a word found already holding the value is a duplicate.
-// The table has at least as many words as the bucket keys, so every insert
-// ends.  Buckets of more than `cap` keys are skipped and set *deferred.
+// leaf could never be a bijection: sort the bucket's w1 words (bitonic, in
+// LDS) and compare neighbours.  Buckets that need more than `cap` words of
+// LDS are skipped and reported in *deferred.
 __global__ void __launch_bounds__(256) k_dupcheck(const Key* keys, const uint64_t* off, uint64_t nb,
-                                                  uint32_t cap, uint32_t tbits, uint32_t* error,
+                                                  uint32_t cap, uint32_t* error,
                                                   uint32_t* deferred) {
   extern __shared__ uint64_t s[];
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
-  const uint32_t size = 1u << tbits;
-  uint64_t* t = s + (uint64_t)wave * size;
-  const uint64_t stride = (uint64_t)gridDim.x * wpb;
-  bool dup = false, defer = false;
-  for (uint64_t j = (uint64_t)blockIdx.x * wpb + wave; j < nb; j += stride) {
+  for (uint64_t j = blockIdx.x; j < nb; j += gridDim.x) {
     const uint64_t o = off[j];
     const uint32_t m = (uint32_t)(off[j + 1] - o);
     if (m < 2) continue;
-    if (m > cap) {
-      defer = true;
+    uint32_t p2 = 1;
+    while (p2 < m) p2 <<= 1;
+    if (p2 > cap) {
+      if (threadIdx.x == 0) atomicOr(deferred, 1u);
       continue;
     }
-    for (uint32_t i = lane; i < size; i += 64) t[i] = 0;
-    uint32_t zeros = 0;
-    for (uint32_t base = 0; base < m; base += 256) {
-      // four loads in flight a lane; lanes past the end read the last key
-      uint64_t w[4];
-#pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
-        const uint32_t i = base + lane + 64u * u;
-        w[u] = keys[o + (i < m ? i : m - 1)].w1;
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
-        if (base + lane + 64u * u >= m) continue;
-        if (w[u] == 0) {
-          ++zeros;
-          continue;
-        }
-        uint32_t h = (uint32_t)((w[u] * 0x9E3779B97F4A7C15ull) >> (64 - tbits));
-        for (;;) {
-          const uint64_t prev =
-              atomicCAS((unsigned long long*)&t[h], 0ull, (unsigned long long)w[u]);
-          if (prev == 0) break;
-          if (prev == w[u]) {
-            dup = true;
-            break;
+    for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) s[i] = i < m ? keys[o + i].w1 : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= p2; k <<= 1) {
+      for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+        for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+          const uint32_t x = i ^ d;
+          if (x > i) {
+            const uint64_t a = s[i], b = s[x];
+            const bool up = (i & k) == 0;
+            if ((a > b) == up) {
+              s[i] = b;
+              s[x] = a;
+            }
           }
-          h = (h + 1) & (size - 1);
         }
+        __syncthreads();
       }
     }
-    for (uint32_t d = 32; d > 0; d >>= 1) zeros += (uint32_t)__shfl_xor((int)zeros, d);
-    if (zeros > 1) dup = true;
+    bool dup = false;
+    for (uint32_t i = threadIdx.x; i + 1 < m; i += blockDim.x) dup |= s[i] == s[i + 1];
+    if (dup) atomicCAS(error, 0u, (uint32_t)(-RS_ERR_DUPLICATE));
+    __syncthreads();
   }
-  if (dup) atomicCAS(error, 0u, (uint32_t)(-RS_ERR_DUPLICATE));
-  if (defer && lane == 0) atomicOr(deferred, 1u);  // the bucket, so `defer`, is the wave's
 }
 
 __global__ void k_init_states(TaskState* st, uint64_t n) {
@@ -449,27 +327,8 @@ hipError_t scan_excl_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t
   return scan_impl<uint64_t>(in, n, out, tmp, s);
 }
 
-// Rows of the chunked counting sort (0: it does not apply; the histogram and
-// the scatter then count with device-wide atomics).  Never more rows than
-// keys per bucket, so rows x nb stays within n words.
-static uint32_t chunk_rows(uint64_t n, uint64_t nb) {
-  if (!n || !nb || nb > kChunkMaxBuckets || n >= (1ull << 32)) return 0;
-  const uint64_t r = n / nb;
-  return r > kChunkMaxRows ? kChunkMaxRows : (r ? (uint32_t)r : 1u);
-}
-
-uint64_t bucket_rows_words(uint64_t n, uint64_t nb) { return (uint64_t)chunk_rows(n, nb) * nb; }
-
-hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* rows,
-                            uint32_t* cnt, uint32_t* maxm, hipStream_t s) {
-  const uint32_t nr = rows ? chunk_rows(n, nb) : 0;
-  if (nr) {
-    const uint64_t chunk = (n + nr - 1) / nr;
-    k_chunk_counts<<<nr, kChunkThreads, (uint32_t)(nb * sizeof(uint32_t)), s>>>(keys, n, nb, chunk,
-                                                                                rows);
-    k_chunk_prefix<<<(uint32_t)((nb + 63) / 64), 1024, 0, s>>>(rows, nr, nb, cnt, maxm);
-    return hipGetLastError();
-  }
+hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* cnt, uint32_t* maxm,
+                            hipStream_t s) {
   if (n) {
     const bool lds = nb <= 16384;
     const uint32_t grid = grid_for(n, 256 * 16, lds ? 512 : 8192);
@@ -480,35 +339,18 @@ hipError_t bucket_histogram(const Key* keys, uint64_t n, uint64_t nb, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint32_t* rows,
-                          const uint64_t* off, uint32_t* fill, Key* out, hipStream_t s) {
+hipError_t bucket_scatter(const Key* keys, uint64_t n, uint64_t nb, const uint64_t* off,
+                          uint32_t* fill, Key* out, hipStream_t s) {
   if (!n) return hipSuccess;
-  const uint32_t nr = rows ? chunk_rows(n, nb) : 0;
-  if (nr) {
-    const uint64_t chunk = (n + nr - 1) / nr;
-    k_chunk_scatter<<<nr, kChunkThreads, (uint32_t)(nb * sizeof(uint32_t)), s>>>(
-        keys, n, nb, chunk, rows, off, out);
-  } else {
-    k_scatter<<<grid_for(n, 256, 16384), 256, 0, s>>>(keys, n, nb, off, fill, out);
-  }
+  k_scatter<<<grid_for(n, 256, 16384), 256, 0, s>>>(keys, n, nb, off, fill, out);
   return hipGetLastError();
 }
 
 hipError_t duplicate_check(const Key* keys, const uint64_t* off, uint64_t nb, uint32_t cap,
-                           uint32_t lds_bytes, uint32_t* error, uint32_t* deferred,
-                           hipStream_t s) {
-  if (cap < 2 || !nb) return hipSuccess;
-  // a table of at least cap words (every insert ends), twice that where the
-  // LDS allows (short probe runs); up to four waves a block within 32 KiB
-  uint32_t tbits = 1;
-  while ((1ull << tbits) < cap) ++tbits;
-  if ((8ull << tbits) > lds_bytes) return hipErrorInvalidValue;
-  if ((16ull << tbits) <= lds_bytes) ++tbits;
-  const uint64_t table = 8ull << tbits;
-  uint32_t wpb = 4;
-  while (wpb > 1 && wpb * table > 32768) wpb >>= 1;
-  k_dupcheck<<<grid_for(nb, wpb, 4096), 64 * wpb, (uint32_t)(wpb * table), s>>>(
-      keys, off, nb, cap, tbits, error, deferred);
+                           uint32_t* error, uint32_t* deferred, hipStream_t s) {
+  if (cap < 2) return hipSuccess;
+  k_dupcheck<<<grid_for(nb, 1, 4096), 256, cap * sizeof(uint64_t), s>>>(keys, off, nb, cap, error,
+                                                                        deferred);
   return hipGetLastError();
 }
 

@@ -65,7 +65,6 @@ SMALL = [
     (1000, 8, 100, False), (1000, 8, 100, True), (3000, 2, 7, True), (3000, 3, 50, False),
     (4000, 4, 30, True), (5000, 5, 100, True), (5000, 7, 300, False), (6000, 10, 500, True),
     (8000, 12, 1000, True), (3000, 12, 60, False), (20000, 8, 100, True), (20000, 6, 1, True),
-    (70000, 4, 1, False),
 ]
 
 
@@ -289,32 +288,6 @@ def test_duplicates_and_bad_arguments():
         assert e.value.code == -1
     # the library is still usable after the errors
     _check_parity(keys, 8, 100, True, "after errors")
-
-
-def test_zero_w1_keys_and_both_sort_paths():
-    """Keys whose second word is zero (the duplicate check's table marks free
-    words with zero and counts such keys instead): one a bucket builds as the
-    oracle does, two in one bucket are a duplicate.  The chunked counting sort
-    (up to 16384 buckets) and the one with device-wide atomics (more buckets)
-    are both covered by the small parity sets."""
-    n, b = 5000, 100
-    keys = keygen.fingerprints(n, 23)
-    nb = oracle.num_buckets(n, b)
-    bucket = [(int(w) * nb) >> 64 for w in keys[:, 0]]
-    first = {}
-    for i, j in enumerate(bucket):
-        first.setdefault(j, i)
-    zeros = list(first.values())[::7]
-    keys[zeros, 1] = 0
-    _check_parity(keys, 8, b, True, "zero w1 in %d buckets" % len(zeros))
-    i = zeros[0]
-    k = next(t for t in range(n) if t != i and bucket[t] == bucket[i])
-    dup = keys.copy()
-    dup[k, 1] = 0
-    _case("two zero w1 keys in one bucket")
-    with pytest.raises(rs().RecSplitError) as e:
-        rs().build(dup, 8, b, True)
-    assert e.value.code == -2
 
 
 def test_stall_guard_stops_a_launch_and_the_library_recovers():
