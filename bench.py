@@ -426,9 +426,11 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, re
         tickets = [srv.submit(k, l, b, True) for k in keys]
         res = [srv.wait(t) for t in tickets]
         t_sat = time.perf_counter() - t0
-        same = all(hashlib.sha256(f.serialize()).digest() == d
+        failed = [{"request": i, "n": r["n"], "status": st}
+                  for i, ((_, st, _), r) in enumerate(zip(res, reqs)) if st != 0]
+        same = all(f is not None and hashlib.sha256(f.serialize()).digest() == d
                    for (f, st, _), d in zip(res, plain_digest))
-        ok = all(st == 0 for (_, st, _) in res)
+        ok = not failed
         del res
         sat_stats = srv.stats()
         lat, wait, span, ok2 = _poisson_served(srv, reqs, keys, l, b)
@@ -454,7 +456,7 @@ def run_served(recsplit, keygen, torch, count, budget_gib, slots, per_launch, re
                         f"(min {min(sizes)}, max {max(sizes)}), l=12, b=1000, rotation, seed 5",
             "keys": total, "hbm_budget_bytes": budget, "slots": slots,
             "max_jobs_per_launch": per_launch, "reserve_per_cu": reserve,
-            "all_ok": ok and ok2, "identical_to_plain": same,
+            "all_ok": ok and ok2, "identical_to_plain": same, "capacity_failed": failed,
             "served_capacity_keys_per_s": total / t_sat,
             "plain_capacity_keys_per_s": total / t_plain,
             "capacity_speedup_vs_plain": t_plain / t_sat,
