@@ -290,6 +290,31 @@ def test_duplicates_and_bad_arguments():
     _check_parity(keys, 8, 100, True, "after errors")
 
 
+def test_extreme_w1_values_and_their_duplicates():
+    """Keys whose second word is 0 or 2^64 - 1 (the duplicate check pads each
+    bucket's sorted w1 words with the latter): one in each of several buckets
+    builds as the oracle does; two equal ones in one bucket are a duplicate."""
+    n, b = 5000, 100
+    keys = keygen.fingerprints(n, 23)
+    nb = oracle.num_buckets(n, b)
+    bucket = [(int(w) * nb) >> 64 for w in keys[:, 0]]
+    first = {}
+    for i, j in enumerate(bucket):
+        first.setdefault(j, i)
+    picks = list(first.values())[::5]
+    keys[picks[0::2], 1] = 0
+    keys[picks[1::2], 1] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    _check_parity(keys, 8, b, True, "w1 = 0 or 2^64-1 in %d buckets" % len(picks))
+    for i in picks[:2]:
+        k = next(t for t in range(n) if t != i and bucket[t] == bucket[i])
+        dup = keys.copy()
+        dup[k, 1] = dup[i, 1]
+        _case("two keys with w1 = %#x in one bucket" % int(dup[i, 1]))
+        with pytest.raises(rs().RecSplitError) as e:
+            rs().build(dup, 8, b, True)
+        assert e.value.code == -2
+
+
 def test_stall_guard_stops_a_launch_and_the_library_recovers():
     """The bug guard on idle time, forced from the host with a 1 microsecond
     limit: the launch ends with RS_ERR_DEVICE instead of finishing, every
